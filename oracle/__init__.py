@@ -1,0 +1,139 @@
+"""ctypes wrapper around the plain FP64 CPU oracle (oracle4.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the benchmark's
+CPU-baseline leg.  The product library never imports, links or executes anything here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle4.c")
+_LIB = os.path.join(_HERE, "liboracle4.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle4.c with gcc (OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, u32, f64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+        L.oracle_rates4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32, f64,
+                                    f64, f64, i32, P, i32, P, P, P, i32]
+        L.oracle_rates4.restype = ctypes.c_int
+        L.oracle_v4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, i32, P, P, P]
+        L.oracle_v4.restype = ctypes.c_int
+        for name in ("oracle_hbar_over_kb", "oracle_c4"):
+            getattr(L, name).restype = f64
+            getattr(L, name).argtypes = []
+        L.oracle_bose.restype = f64
+        L.oracle_bose.argtypes = [f64, f64]
+        L.oracle_delta.restype = f64
+        L.oracle_delta.argtypes = [f64, f64, f64]
+        L.oracle_default_dq.restype = f64
+        L.oracle_default_dq.argtypes = [P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Model:
+    """Contiguous copies of one instance's arrays in the layouts the oracle expects."""
+
+    def __init__(self, grid, mass, omega, evec, vel, atoms, cells, phi):
+        self.grid = np.ascontiguousarray(grid, dtype=np.int32)
+        self.mass = np.ascontiguousarray(mass, dtype=np.float64)
+        self.omega = np.ascontiguousarray(omega, dtype=np.float64)
+        ev = np.ascontiguousarray(evec, dtype=np.complex128)
+        self.evec = ev.view(np.float64)
+        self.vel = np.ascontiguousarray(vel, dtype=np.float64)
+        self.atoms = np.ascontiguousarray(atoms, dtype=np.int32)
+        self.cells = np.ascontiguousarray(cells, dtype=np.int32)
+        self.phi = np.ascontiguousarray(phi, dtype=np.float64)
+        self.natoms = int(self.mass.shape[0])
+        self.nb = 3 * self.natoms
+        self.nq = int(np.prod(self.grid))
+
+    @classmethod
+    def from_instance(cls, inst, phi_scale: float = 1.0):
+        return cls(inst.grid, inst.cr.mass, inst.omega, inst.evec, inst.vel, inst.fc4.atoms,
+                   inst.fc4.cells, inst.fc4.phi * phi_scale)
+
+    def _common(self):
+        return [_p(self.grid), self.natoms, _p(self.mass), _p(self.omega), _p(self.evec),
+                _p(self.vel), int(self.atoms.shape[0]), _p(self.atoms), _p(self.cells),
+                _p(self.phi)]
+
+
+def default_dq(A, grid) -> float:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    g = np.ascontiguousarray(grid, dtype=np.int32)
+    return float(lib().oracle_default_dq(_p(A), _p(g)))
+
+
+def rates4(model: Model, T, scalebroad, mask, dq, targets=None, window_w=2.0,
+           sigma_min=1e-4, want_rates=True, nthreads=0):
+    """Returns (rates[nT][nt], rates_ch[nT][3][nt], counts[nt][3])."""
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    if targets is None:
+        targets = np.arange(model.nq * model.nb)
+    targets = np.ascontiguousarray(targets, dtype=np.int32)
+    nt = int(targets.shape[0])
+    rates = np.zeros((len(T), nt))
+    rch = np.zeros((len(T), 3, nt))
+    counts = np.zeros((nt, 3), dtype=np.int64)
+    rc = lib().oracle_rates4(*model._common(), _p(T), len(T), float(scalebroad), int(mask),
+                             float(window_w), float(sigma_min), float(dq), nt, _p(targets),
+                             1 if want_rates else 0, _p(rates), _p(rch), _p(counts),
+                             int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_rates4 returned {rc}")
+    return rates, rch, counts
+
+
+def v4(model: Model, modes4, signs4) -> np.ndarray:
+    """V (Eq. V4) for explicit processes: modes4[n][4] mode ids, signs4[n][4] slot signs."""
+    modes4 = np.ascontiguousarray(modes4, dtype=np.int32).reshape(-1, 4)
+    signs4 = np.ascontiguousarray(signs4, dtype=np.int32).reshape(-1, 4)
+    n = modes4.shape[0]
+    V = np.zeros(n, dtype=np.complex128)
+    lib().oracle_v4(*model._common(), n, _p(modes4), _p(signs4), _p(V.view(np.float64)))
+    return V
+
+
+def c4() -> float:
+    return float(lib().oracle_c4())
+
+
+def hbar_over_kb() -> float:
+    return float(lib().oracle_hbar_over_kb())
+
+
+def bose(omega, T) -> float:
+    return float(lib().oracle_bose(float(omega), float(T)))
+
+
+def delta(dw, sigma2, sigma_min=1e-4) -> float:
+    return float(lib().oracle_delta(float(dw), float(sigma2), float(sigma_min)))

@@ -1,0 +1,378 @@
+/*
+ * oracle4.c -- plain, slow FP64 CPU reference for the four-phonon RTA scattering rate.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or calls this
+ * file; only the tests, the smoke check and the benchmark's CPU-baseline leg use it.
+ *
+ * What it computes (FourPhonon paper, Sec. 2.2 and 2.4):
+ *   1/tau_4ph(lambda) = (1/N) [ sum^{++} 1/2 G^{++} + sum^{+-} 1/2 G^{+-} + sum^{--} 1/6 G^{--} ]
+ *     (the four-phonon bracket of Eq. tao0), with the sums unrestricted over
+ *     lambda' = (q',j'), lambda'' = (q'',j'') and j''', and q''' fixed by momentum
+ *     conservation q''' = q +- q' +- q'' + Q (the definition that follows Eq. tao0);
+ *   G^{(s)} from Eq. 4phgamma (prefactor hbar^2 pi / (8N), occupation factors over n0_lambda,
+ *     |V|^2, delta / (w w' w'' w'''));
+ *   V from Eq. V4 (sum over quartets and Cartesian indices of Phi times four eigenvector
+ *     components over sqrt of the four masses, times the three lattice phases);
+ *   delta from the adaptive Gaussian of Sec. 2.4 with sigma = |v'' - v'''| |dq| (App. B),
+ *     scaled by scalebroad, and replaced by 1 when sigma is very small.
+ *
+ * Readings where the paper is silent (also used by the library; both sides implement them
+ * separately):
+ *   - a process is kept only if |dw| <= W sigma (evaluated squared), W = window_w;
+ *   - "sigma very small" means sigma^2 < sigma_min^2, and then delta := 1 (ps);
+ *   - a mode with omega <= 0 is inactive: it has rate 0 and takes part in no process;
+ *   - e^{-lambda} = conj(e^{lambda}); phases exp(i q.R) use lattice vectors only and an
+ *     integer reduction of q.R, so exp(i G.R) = 1 exactly;
+ *   - the predicate is evaluated in a fixed FP64 order with no contraction:
+ *       dw  = ((w  s0 w') s1 w'') - w'''     (s0, s1 the channel signs, left to right)
+ *       d   = v'' - v'''  (component-wise),   s2 = (dx*dx + dy*dy) + dz*dz
+ *       keep <=> dw*dw <= c_win * s2,         c_win = ((W*sb)*dq) * ((W*sb)*dq)
+ *   - units: omega rad/ps, v A/ps, Phi eV/A^4, mass amu, T K, rates 1/ps.
+ *
+ * Evaluation order of V: per quartet n, the slot-1 and slot-2 factors are contracted first
+ * (they are fixed while the loops over q'' and branches run) and the result is then
+ * contracted with the slot-3 and slot-4 factors.  Nothing is grouped across quartets.
+ *
+ * Compile with -O2 -ffp-contract=off so that the predicate is bit-reproducible.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <complex.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double _Complex cplx;
+
+/* SI 2019 exact values (h, k_B, e) and CODATA 2018 (amu) */
+#define HBAR (6.62607015e-34 / (2.0 * M_PI))  /* J s   */
+static const double KB = 1.380649e-23;        /* J/K   */
+static const double EV = 1.602176634e-19;     /* J     */
+static const double AMU = 1.66053906660e-27;  /* kg    */
+static const double ANG = 1.0e-10;            /* m     */
+
+/* hbar/k_B in K*ps */
+double oracle_hbar_over_kb(void) { return HBAR / KB * 1.0e12; }
+
+/* Prefactor of Eq. 4phgamma without the 1/N factors:
+ *   G[1/ps] = C4 * occ * |V|^2 * delta[ps] / (w w' w'' w''')[(rad/ps)^4]
+ * for V in eV / (A^4 amu^2):  C4 = hbar^2 pi / 8 * (eV/(A^4 amu^2))^2 * 1e-72. */
+double oracle_c4(void) {
+    const double kv = EV / (ANG * ANG * ANG * ANG * AMU * AMU);
+    return HBAR * HBAR * M_PI / 8.0 * kv * kv * 1.0e-72;
+}
+
+/* Bose-Einstein occupation n0 (after Eq. 4phgamma). */
+double oracle_bose(double omega, double T) {
+    return 1.0 / expm1(oracle_hbar_over_kb() * omega / T);
+}
+
+/* Adaptive Gaussian delta (Sec. 2.4): exp(-dw^2/sigma^2) / (sqrt(pi) sigma), or 1 when
+ * sigma^2 < sigma_min^2. */
+double oracle_delta(double dw, double sigma2, double sigma_min) {
+    if (sigma2 < sigma_min * sigma_min) return 1.0;
+    return exp(-(dw * dw) / sigma2) / (sqrt(M_PI) * sqrt(sigma2));
+}
+
+typedef struct {
+    int g[3];
+    int N;
+    int nat, nb;
+    const double *mass, *omega, *evec, *vel;
+    int nq4;
+    const int32_t *atoms, *cells;
+    const double *phi;
+    cplx *rou;          /* exp(2 pi i k / N), exactly conjugate-symmetric */
+} model_t;
+
+static void model_init(model_t *m, const int32_t grid[3], int32_t natoms, const double *mass,
+                       const double *omega, const double *evec, const double *vel,
+                       int32_t nq4, const int32_t *atoms, const int32_t *cells,
+                       const double *phi) {
+    m->g[0] = grid[0]; m->g[1] = grid[1]; m->g[2] = grid[2];
+    m->N = grid[0] * grid[1] * grid[2];
+    m->nat = natoms; m->nb = 3 * natoms;
+    m->mass = mass; m->omega = omega; m->evec = evec; m->vel = vel;
+    m->nq4 = nq4; m->atoms = atoms; m->cells = cells; m->phi = phi;
+    m->rou = (cplx *)malloc(sizeof(cplx) * (size_t)m->N);
+    for (int k = 0; k <= m->N / 2; ++k) {
+        double a = 2.0 * M_PI * (double)k / (double)m->N;
+        m->rou[k] = cos(a) + I * sin(a);
+    }
+    for (int k = m->N / 2 + 1; k < m->N; ++k) m->rou[k] = conj(m->rou[m->N - k]);
+}
+
+static void model_free(model_t *m) { free(m->rou); }
+
+static void qtriple(const model_t *m, int iq, int n[3]) {
+    n[0] = iq % m->g[0];
+    n[1] = (iq / m->g[0]) % m->g[1];
+    n[2] = iq / (m->g[0] * m->g[1]);
+}
+
+static int imod(int a, int b) { int r = a % b; return r < 0 ? r + b : r; }
+
+/* q''' = q + s1 q' + s2 q'' folded back into the grid (momentum conservation with the
+ * Umklapp vector Q absorbed). */
+static int fold(const model_t *m, int iq, int s1, int iq1, int s2, int iq2) {
+    int a[3], b[3], c[3], r[3];
+    qtriple(m, iq, a); qtriple(m, iq1, b); qtriple(m, iq2, c);
+    for (int d = 0; d < 3; ++d) r[d] = imod(a[d] + s1 * b[d] + s2 * c[d], m->g[d]);
+    return r[0] + m->g[0] * (r[1] + m->g[1] * r[2]);
+}
+
+/* exp(i q.R) for grid point iq and integer cell R (lattice coordinates). */
+static cplx phase(const model_t *m, int iq, const int32_t *R) {
+    int n[3]; qtriple(m, iq, n);
+    long k = 0;
+    for (int d = 0; d < 3; ++d) k += (long)imod(n[d] * R[d], m->g[d]) * (m->N / m->g[d]);
+    return m->rou[k % m->N];
+}
+
+static cplx ev(const model_t *m, int iq, int j, int atom, int x) {
+    const double *p = m->evec + 2 * ((((size_t)iq * m->nb + j) * m->nat + atom) * 3 + x);
+    return p[0] + I * p[1];
+}
+
+/* Factor of one slot of Eq. V4: e_x^{+-lambda}(atom) exp(+-i q.R) / sqrt(M_atom). */
+static cplx slot_factor(const model_t *m, int sign, int iq, int j, int atom, const int32_t *R,
+                        int x) {
+    cplx f = ev(m, iq, j, atom, x) * phase(m, iq, R) / sqrt(m->mass[atom]);
+    return sign > 0 ? f : conj(f);
+}
+
+static const int32_t ZERO_CELL[3] = {0, 0, 0};
+
+/* V of Eq. V4 for four modes with slot signs sg[0..3] (slot 1 is the target, sign +1 in
+ * the rate; the general form is used by the permutation tests).  The quartet's slot-1
+ * atom sits in the home cell. */
+static cplx v4_general(const model_t *m, const int mode[4], const int sg[4]) {
+    cplx V = 0.0;
+    for (int n = 0; n < m->nq4; ++n) {
+        const int32_t *at = m->atoms + 4 * n;
+        const int32_t *cl = m->cells + 9 * n;
+        const double *ph = m->phi + 81 * (size_t)n;
+        cplx X[4][3];
+        for (int s = 0; s < 4; ++s) {
+            const int32_t *R = s == 0 ? ZERO_CELL : cl + 3 * (s - 1);
+            int iq = mode[s] / m->nb, j = mode[s] % m->nb;
+            for (int x = 0; x < 3; ++x) X[s][x] = slot_factor(m, sg[s], iq, j, at[s], R, x);
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int c = 0; c < 3; ++c)
+                    for (int d = 0; d < 3; ++d)
+                        V += ph[((a * 3 + b) * 3 + c) * 3 + d] * X[0][a] * X[1][b] * X[2][c] * X[3][d];
+    }
+    return V;
+}
+
+/* Public: V for n explicit processes.  modes4[n][4] are mode ids iq*nb + j, signs4[n][4]
+ * are the slot signs (+1: e^{lambda} e^{+iq.R}; -1: the complex conjugate).  Output V
+ * interleaved (re, im). */
+int oracle_v4(const int32_t grid[3], int32_t natoms, const double *mass, const double *omega,
+              const double *evec, const double *vel, int32_t nq4, const int32_t *atoms,
+              const int32_t *cells, const double *phi, int32_t n, const int32_t *modes4,
+              const int32_t *signs4, double *V) {
+    model_t m;
+    model_init(&m, grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi);
+    for (int i = 0; i < n; ++i) {
+        int md[4], sg[4];
+        for (int s = 0; s < 4; ++s) { md[s] = modes4[4 * i + s]; sg[s] = signs4[4 * i + s]; }
+        cplx v = v4_general(&m, md, sg);
+        V[2 * i] = creal(v); V[2 * i + 1] = cimag(v);
+    }
+    model_free(&m);
+    return 0;
+}
+
+/* The three channels of Eq. 4phgamma: signs of lambda' and lambda'' and the weight of
+ * each in Eq. tao0. */
+static const int CH_S1[3] = {+1, +1, -1};
+static const int CH_S2[3] = {+1, -1, -1};
+static const double CH_W[3] = {0.5, 0.5, 1.0 / 6.0};
+
+/* Energy-window predicate (fixed FP64 order, see header). */
+static int keep_process(const model_t *m, int ch, int mu, int mu1, int mu2, int mu3,
+                        double c_win, double *dw_out, double *s2_out) {
+    const double w = m->omega[mu], w1 = m->omega[mu1], w2 = m->omega[mu2], w3 = m->omega[mu3];
+    double a = CH_S1[ch] > 0 ? w + w1 : w - w1;
+    double b = CH_S2[ch] > 0 ? a + w2 : a - w2;
+    double dw = b - w3;
+    const double *v2 = m->vel + 3 * (size_t)mu2, *v3 = m->vel + 3 * (size_t)mu3;
+    double dx = v2[0] - v3[0], dy = v2[1] - v3[1], dz = v2[2] - v3[2];
+    double s2 = (dx * dx + dy * dy) + dz * dz;
+    *dw_out = dw; *s2_out = s2;
+    return dw * dw <= c_win * s2;
+}
+
+static void neumaier(double *sum, double *comp, double x) {
+    double t = *sum + x;
+    if (fabs(*sum) >= fabs(x)) *comp += (*sum - t) + x;
+    else *comp += (x - t) + *sum;
+    *sum = t;
+}
+
+/*
+ * Public: four-phonon RTA rates for a list of target modes.
+ *   rates[nT][ntargets]            1/ps  (required)
+ *   rates_ch[nT][3][ntargets]      per channel (++, +-, --), optional
+ *   counts[ntargets][3]            number of kept processes per channel, optional
+ * If want_rates == 0 only the counts are produced (no matrix elements are evaluated).
+ * Returns 0, or -1 on invalid arguments.
+ */
+int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
+                  const double *omega, const double *evec, const double *vel, int32_t nq4,
+                  const int32_t *atoms, const int32_t *cells, const double *phi,
+                  const double *T, int32_t nT, double scalebroad, uint32_t mask,
+                  double window_w, double sigma_min, double dq, int32_t ntargets,
+                  const int32_t *targets, int32_t want_rates, double *rates,
+                  double *rates_ch, int64_t *counts, int32_t nthreads) {
+    if (natoms <= 0 || nT <= 0 || ntargets < 0 || scalebroad <= 0.0 || dq <= 0.0) return -1;
+    model_t m;
+    model_init(&m, grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi);
+    const int N = m.N, nb = m.nb, nmodes = N * nb;
+    const double c_win = ((window_w * scalebroad) * dq) * ((window_w * scalebroad) * dq);
+    const double c_sig = (scalebroad * dq) * (scalebroad * dq);
+    const double C4 = oracle_c4();
+    const double inv_n2 = 1.0 / ((double)N * (double)N);
+    const double hk = oracle_hbar_over_kb();
+
+    /* n0 for every mode and temperature (0 for inactive modes, never used) */
+    double *occ = (double *)calloc((size_t)nT * nmodes, sizeof(double));
+    for (int t = 0; t < nT; ++t)
+        for (int mu = 0; mu < nmodes; ++mu)
+            if (omega[mu] > 0.0) occ[(size_t)t * nmodes + mu] = 1.0 / expm1(hk * omega[mu] / T[t]);
+
+    /* partial sums per (target, q') so that the parallel loop has a fixed summation order */
+    const size_t npart = (size_t)ntargets * N;
+    double *part = (double *)calloc(npart * nT * 3 * 2, sizeof(double)); /* sum, comp */
+    int64_t *pcnt = (int64_t *)calloc(npart * 3, sizeof(int64_t));
+
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        cplx *W = (cplx *)malloc(sizeof(cplx) * (size_t)(m.nq4 > 0 ? m.nq4 : 1) * 9);
+#pragma omp for schedule(dynamic, 1)
+        for (long long task = 0; task < (long long)npart; ++task) {
+            const int it = (int)(task / N), iq1 = (int)(task % N);
+            const int mu = targets[it];
+            const int iq = mu / nb, j = mu % nb;
+            double *P = part + (size_t)task * nT * 3 * 2;
+            int64_t *C = pcnt + (size_t)task * 3;
+            if (omega[mu] <= 0.0) continue;
+            for (int ch = 0; ch < 3; ++ch) {
+                if (!(mask & (1u << ch))) continue;
+                const int s1 = CH_S1[ch], s2 = CH_S2[ch];
+                for (int j1 = 0; j1 < nb; ++j1) {
+                    const int mu1 = iq1 * nb + j1;
+                    if (omega[mu1] <= 0.0) continue;
+                    /* slot-1 x slot-2 partial contraction per quartet:
+                     * W_n^{gt} = sum_{ab} Phi_n^{abgt} X1_n^a X2_n^b */
+                    if (want_rates) {
+                        for (int n = 0; n < m.nq4; ++n) {
+                            const int32_t *at = m.atoms + 4 * n;
+                            const int32_t *cl = m.cells + 9 * n;
+                            const double *ph = m.phi + 81 * (size_t)n;
+                            cplx X1[3], X2[3];
+                            for (int x = 0; x < 3; ++x) {
+                                X1[x] = slot_factor(&m, +1, iq, j, at[0], ZERO_CELL, x);
+                                X2[x] = slot_factor(&m, s1, iq1, j1, at[1], cl, x);
+                            }
+                            for (int c = 0; c < 3; ++c)
+                                for (int d = 0; d < 3; ++d) {
+                                    cplx acc = 0.0;
+                                    for (int a = 0; a < 3; ++a)
+                                        for (int b = 0; b < 3; ++b)
+                                            acc += ph[((a * 3 + b) * 3 + c) * 3 + d] * X1[a] * X2[b];
+                                    W[9 * n + 3 * c + d] = acc;
+                                }
+                        }
+                    }
+                    for (int iq2 = 0; iq2 < N; ++iq2) {
+                        const int iq3 = fold(&m, iq, s1, iq1, s2, iq2);
+                        for (int j2 = 0; j2 < nb; ++j2) {
+                            const int mu2 = iq2 * nb + j2;
+                            if (omega[mu2] <= 0.0) continue;
+                            for (int j3 = 0; j3 < nb; ++j3) {
+                                const int mu3 = iq3 * nb + j3;
+                                if (omega[mu3] <= 0.0) continue;
+                                double dw, s2v;
+                                if (!keep_process(&m, ch, mu, mu1, mu2, mu3, c_win, &dw, &s2v)) continue;
+                                C[ch] += 1;
+                                if (!want_rates) continue;
+                                /* V = sum_n sum_{gt} W_n^{gt} X3_n^g X4_n^t  (Eq. V4) */
+                                cplx V = 0.0;
+                                for (int n = 0; n < m.nq4; ++n) {
+                                    const int32_t *at = m.atoms + 4 * n;
+                                    const int32_t *cl = m.cells + 9 * n;
+                                    cplx X3[3], X4[3];
+                                    for (int x = 0; x < 3; ++x) {
+                                        X3[x] = slot_factor(&m, s2, iq2, j2, at[2], cl + 3, x);
+                                        X4[x] = slot_factor(&m, -1, iq3, j3, at[3], cl + 6, x);
+                                    }
+                                    for (int c = 0; c < 3; ++c)
+                                        for (int d = 0; d < 3; ++d)
+                                            V += W[9 * n + 3 * c + d] * X3[c] * X4[d];
+                                }
+                                const double v2 = creal(V) * creal(V) + cimag(V) * cimag(V);
+                                const double delta = oracle_delta(dw, c_sig * s2v, sigma_min);
+                                const double wprod = omega[mu] * omega[mu1] * omega[mu2] * omega[mu3];
+                                for (int t = 0; t < nT; ++t) {
+                                    const double *n0 = occ + (size_t)t * nmodes;
+                                    double f;
+                                    /* occupation factors of Eq. 4phgamma */
+                                    if (ch == 0) f = (1.0 + n0[mu1]) * (1.0 + n0[mu2]) * n0[mu3] / n0[mu];
+                                    else if (ch == 1) f = (1.0 + n0[mu1]) * n0[mu2] * n0[mu3] / n0[mu];
+                                    else f = n0[mu1] * n0[mu2] * n0[mu3] / n0[mu];
+                                    const double G = C4 * inv_n2 * f * v2 * delta / wprod;
+                                    neumaier(&P[(t * 3 + ch) * 2], &P[(t * 3 + ch) * 2 + 1], CH_W[ch] * G);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        free(W);
+    }
+
+    /* ordered reduction over q' */
+    for (int it = 0; it < ntargets; ++it) {
+        int64_t cc[3] = {0, 0, 0};
+        for (int t = 0; t < nT; ++t) {
+            double tot = 0.0, totc = 0.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                double s = 0.0, c = 0.0;
+                for (int iq1 = 0; iq1 < N; ++iq1) {
+                    const double *P = part + ((size_t)it * N + iq1) * nT * 3 * 2;
+                    neumaier(&s, &c, P[(t * 3 + ch) * 2]);
+                    c += P[(t * 3 + ch) * 2 + 1];
+                }
+                if (rates_ch) rates_ch[((size_t)t * 3 + ch) * ntargets + it] = s + c;
+                neumaier(&tot, &totc, s + c);
+            }
+            rates[(size_t)t * ntargets + it] = tot + totc;
+        }
+        for (int iq1 = 0; iq1 < N; ++iq1)
+            for (int ch = 0; ch < 3; ++ch) cc[ch] += pcnt[((size_t)it * N + iq1) * 3 + ch];
+        if (counts) for (int ch = 0; ch < 3; ++ch) counts[3 * (size_t)it + ch] = cc[ch];
+    }
+    free(part); free(pcnt); free(occ);
+    model_free(&m);
+    return 0;
+}
+
+/* Default |dq| reading: (|det B| / N)^(1/3), B the reciprocal vectors (2 pi included).
+ * A holds the lattice vectors as rows (Angstrom). */
+double oracle_default_dq(const double A[9], const int32_t grid[3]) {
+    const double detA = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                        A[2] * (A[3] * A[7] - A[4] * A[6]);
+    const double detB = pow(2.0 * M_PI, 3) / fabs(detA);
+    const double N = (double)grid[0] * grid[1] * grid[2];
+    return cbrt(detB / N);
+}
