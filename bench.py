@@ -1,0 +1,182 @@
+"""Benchmark of the four-phonon RTA rate kernel on one MI355X.
+
+One step = the whole rate computation (occupations, per-target precontraction, fused
+enumeration / window prefilter / contraction / accumulation kernel, ordered reduction) for
+every mode of the 8x8x8 diamond-structure workload (3072 modes, second-shell FC4 with 1522
+quartets, T = 300 and 1000 K, scalebroad 1, all three channels), inputs resident in HBM.
+
+Prints one JSON line.  `value` is kept four-phonon processes per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6e12      # MI355X FP64 vector FLOP/s
+PEAK_FP32_VALU = 157.3e12
+
+
+def algorithmic_flops(stats, inst, n_pairs):
+    """Algorithmic FLOPs of one main-kernel launch (per-unit figures in the design doc):
+    prefilter 12 per candidate, W'' build 456 per combo per (lambda, lambda') pair,
+    branch block 72 ng + 16 nb^3 per contracted block, Gamma 40 + 6 nT per kept process."""
+    from paper_2104_04895_amd import Context  # noqa: F401  (binding only)
+    ng, nc, nb = inst["ng"], inst["nc"], inst["nb"]
+    nT = inst["nT"]
+    return (12.0 * stats["candidates"] + 456.0 * nc * n_pairs
+            + (72.0 * ng + 16.0 * nb ** 3) * stats["blocks"]
+            + (40.0 + 6.0 * nT) * stats["processes"])
+
+
+def groups_and_combos(fc4):
+    g, c = set(), set()
+    for n in range(fc4.n):
+        i, j, k, l = (int(x) for x in fc4.atoms[n])
+        Rj, Rk, Rl = (tuple(int(v) for v in fc4.cells[n, s]) for s in range(3))
+        d = tuple(a - b for a, b in zip(Rk, Rl))
+        a = tuple(x - y for x, y in zip(Rj, Rl))
+        g.add((k, l, d))
+        c.add((k, l, d, j, a))
+    return len(g), len(c)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 side measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the rate kernel runs on a single MI355X and "
+              f"--gpus {args.gpus} is not supported (multi-GPU sharding is a design note).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2104_04895_amd as fp4
+
+    t_setup = time.time()
+    inst = synth.medium()
+    dq = (abs(np.linalg.det(inst.cr.B)) / inst.nq) ** (1.0 / 3.0)
+    ng, nc = groups_and_combos(inst.fc4)
+    nmodes = inst.nmodes
+    nT = len(inst.T)
+    dev = torch.device("cuda:0")
+    ctx = fp4.Context(0)
+    ctx.load_instance(inst, dq=dq)
+    ctx.set_param(fp4.FP4_PARAM_PROFILE, 1)
+    prec = fp4.FP4_FP64 if args.precision == "fp64" else fp4.FP4_FP32
+    d_rates = torch.empty((nT, nmodes), dtype=torch.float64, device=dev)
+    d_counts = torch.empty((nmodes, 3), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(precision):
+        ctx.compute_rates4_async(inst.T, inst.scalebroad, inst.mask, precision,
+                                 stream.cuda_stream, d_rates.data_ptr(), 0, d_counts.data_ptr())
+
+    for _ in range(args.warmup):
+        step(prec)
+    torch.cuda.synchronize()
+    print(f"# setup {time.time() - t_setup:.1f}s; timing {args.steps} steps", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    main_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.steps):
+        step(prec)
+        main_ms.append(ctx.last_timing()["ms_main"])
+        print(f"# step {k} main kernel {main_ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_events = ev0.elapsed_time(ev1)
+    ms_per_step = ms_events / args.steps
+    counts = d_counts.cpu().numpy()
+    processes = int(counts.sum())
+    rates64 = d_rates.cpu().numpy().copy()
+
+    # candidates: active targets x active partner modes^2 x nb x enabled channels
+    act = int((inst.omega.reshape(-1) > 0).sum())
+    nch = bin(inst.mask).count("1")
+    # per active target: active lambda' x (N q'' x nb j'') x nb j''' per channel
+    candidates = act * act * inst.nq * inst.nb * inst.nb * nch
+    stats = {"processes": processes, "candidates": candidates}
+    lib_stats = ctx.last_stats()
+    stats["blocks"] = lib_stats["blocks"]
+    n_pairs = act * act
+    flops = algorithmic_flops(stats, {"ng": ng, "nc": nc, "nb": inst.nb, "nT": nT}, n_pairs)
+    t_main = float(np.mean(main_ms)) / 1e3
+    peak = PEAK_FP64_VALU if prec == fp4.FP4_FP64 else PEAK_FP32_VALU
+    achieved = flops / t_main
+
+    extras = {}
+    if not args.no_fp32 and prec == fp4.FP4_FP64:
+        step(fp4.FP4_FP32)
+        torch.cuda.synchronize()
+        ms32 = ctx.last_timing()["ms_main"]
+        r32 = d_rates.cpu().numpy()
+        rel = np.abs(r32 - rates64) / np.maximum(np.abs(rates64), 1e-300)
+        rel[rates64 == 0] = 0.0
+        extras["fp32_contraction"] = {"ms_main_kernel": ms32, "speedup_vs_fp64_main": t_main * 1e3 / ms32,
+                                      "max_rel_err_vs_fp64_path": float(rel.max()),
+                                      "median_rel_err_vs_fp64_path": float(np.median(rel[rates64 > 0]))}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        m = oracle.Model.from_instance(inst)
+        q1 = np.arange(0, inst.nq, 16)
+        target = [100]
+        t1 = time.perf_counter()
+        _, c_o = oracle.rates4_partners(m, inst.T, inst.scalebroad, inst.mask, dq, target, q1)
+        dt = time.perf_counter() - t1
+        nproc = int(c_o.sum())
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": nproc / dt, "unit": "processes/s", "cores": cores, "kind": "oracle",
+               "sample": f"1 target mode x {len(q1)} of {inst.nq} partner q' points of the "
+                         f"8x8x8 workload, both temperatures ({nproc} processes, {dt:.1f} s)"}
+
+    out = {
+        "metric": "4ph processes/sec and rates time-to-solution; FP64 vs mixed at stated rel. err",
+        "value": processes / (ms_per_step / 1e3),
+        "unit": "processes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == fp4.FP4_FP64 else "f32-contraction/f64",
+        "data": "synthetic",
+        "config": {"workload": "diamond-structure 2-atom cell, 8x8x8 Gamma grid (3072 modes), "
+                               "second-shell FC4 (1522 quartets), T=300,1000 K, scalebroad 1, "
+                               "channels ++,+-,--",
+                   "modes": nmodes, "temperatures": list(inst.T), "processes_per_step": processes,
+                   "wall_s_timed": wall},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_rates", "kernel_ms": t_main * 1e3,
+                     "algorithmic_flops": flops},
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * fp4.h -- C ABI of the MI355X four-phonon RTA scattering-rate library.
+ *
+ * The library evaluates the four-phonon bracket of the single-mode relaxation-time rate
+ * (FourPhonon paper, Eq. tao0) for every mode of a Gamma-centred q-grid:
+ *
+ *   1/tau_4ph(lambda) = sum over lambda' = (q',j'), lambda'' = (q'',j''), j''' of
+ *       1/2 G^{++} + 1/2 G^{+-} + 1/6 G^{--}     (1/N and 1/N factors included)
+ *
+ * with q''' = q +- q' +- q'' + Q fixed by momentum conservation (Sec. 2.2), G from
+ * Eq. 4phgamma, the matrix element V from Eq. V4 and the adaptive Gaussian
+ * delta(dw) = exp(-dw^2/sigma^2)/(sqrt(pi) sigma), sigma = scalebroad |v'' - v'''| |dq|
+ * (Sec. 2.4 and App. B).  A process takes part only if |dw| <= W sigma (W = window width,
+ * default 2; the test is evaluated squared in a fixed FP64 order), and delta is set to 1 when
+ * sigma^2 < sigma_min^2 (the paper's small-sigma correction, Sec. 2.4).
+ *
+ * Units: omega rad/ps, v Angstrom/ps, q 1/Angstrom (2 pi included), Phi eV/Angstrom^4,
+ * mass amu, T kelvin, rates 1/ps.
+ *
+ * Conventions of the inputs (they fix what Eq. V4 means):
+ *   - lattice vectors are the ROWS of A (Angstrom); grid point iq = n1 + N1*(n2 + N2*n3) is
+ *     q = sum_d (n_d/N_d) b_d, n_d in [0, N_d);
+ *   - mode id mu = iq*nb + j, nb = 3*natoms;
+ *   - eigenvectors diagonalise D(q) = sum_R Phi2(0a,Rb) exp(+i q.R)/sqrt(Ma Mb) (phases on
+ *     lattice vectors only), are normalised to 1, and e^{-lambda} = conj(e^{lambda});
+ *   - omega <= 0 marks a mode inactive: its rate is 0 and it takes part in no process.
+ *
+ * Error convention: every int-returning call returns FP4_OK (0) or a negative code; no
+ * exception crosses the ABI; the context stays usable after an error and fp4_last_error()
+ * gives the reason.  All host pointers belong to the caller and are only read (or, for
+ * outputs, written) during the call; the library keeps its own device copies.  A context
+ * must not be used from two host threads at once.
+ */
+#ifndef FP4_H
+#define FP4_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FP4_OK 0
+#define FP4_E_INVAL (-1)       /* bad shape, range, NaN/Inf, mask 0, T <= 0, sb <= 0 */
+#define FP4_E_STATE (-2)       /* compute before load, inconsistent loads */
+#define FP4_E_NOMEM (-3)       /* device or host allocation failed */
+#define FP4_E_DEVICE (-4)      /* a HIP runtime call failed (text in fp4_last_error) */
+#define FP4_E_UNSUPPORTED (-5) /* option not supported for these inputs */
+
+/* arithmetic of the matrix-element contraction (the window predicate, occupations, the
+ * Gaussian and all rate sums are FP64 in every mode) */
+#define FP4_FP64 0   /* complex FP64 contraction */
+#define FP4_FP32 1   /* complex FP32 contraction and |V|^2, promoted to FP64 */
+
+/* keys of fp4_set_param */
+#define FP4_PARAM_WINDOW_W 1      /* W of the window |dw| <= W sigma (default 2.0) */
+#define FP4_PARAM_SIGMA_MIN 2     /* sigma below which delta := 1, rad/ps (default 1e-4) */
+#define FP4_PARAM_QCHUNK 3        /* q' points per work-group (0 = automatic) */
+#define FP4_PARAM_PROFILE 4       /* 1: time every kernel with HIP events (fp4_last_timing) */
+
+/* channel bits of the process mask (Eq. 4phgamma): recombination, redistribution, splitting */
+#define FP4_PP 1u
+#define FP4_PM 2u
+#define FP4_MM 4u
+
+typedef struct fp4_ctx fp4_ctx;
+
+/* Create a context on HIP device `device_id`.  *out receives the handle (NULL on error).
+ * Returns FP4_E_DEVICE if the device cannot be used. */
+int fp4_create(fp4_ctx **out, int device_id);
+
+/* Release every device and host resource of the context (NULL is ignored). */
+void fp4_destroy(fp4_ctx *ctx);
+
+/* Lattice and grid (Sec. 2.2: N is the number of grid points).
+ *   A[9]      lattice vectors as rows, Angstrom (non-singular)
+ *   grid[3]   N1, N2, N3 >= 1, N = N1 N2 N3 <= 2^20
+ *   natoms    1..16 atoms in the cell; nb = 3*natoms branches
+ *   mass      [natoms] amu, > 0
+ *   dq        |Delta q''| of the adaptive broadening (App. B), 1/Angstrom; <= 0 selects
+ *             (|det B|/N)^(1/3), the cube root of the reciprocal volume per grid point.
+ * Invalidates previously loaded modes and force constants. */
+int fp4_load_lattice(fp4_ctx *ctx, const double A[9], const int32_t grid[3], int32_t natoms,
+                     const double *mass, double dq);
+
+/* Harmonic modes on the full grid (copied to the device).
+ *   nq = N, nb = 3*natoms (else FP4_E_STATE)
+ *   omega [nq][nb]                 rad/ps (omega <= 0: inactive mode)
+ *   evec  [nq][nb][natoms][3]      complex, interleaved (re, im)
+ *   vel   [nq][nb][3]              Angstrom/ps
+ * Non-finite values give FP4_E_INVAL. */
+int fp4_load_modes(fp4_ctx *ctx, int32_t nq, int32_t nb, const double *omega,
+                   const double *evec, const double *vel);
+
+/* Fourth-order force constants as a quartet list (Eq. V4, Eq. PE):
+ *   atoms [n][4]      basis indices (i, j, k, l) in [0, natoms)
+ *   cells [n][3][3]   integer lattice coordinates of the cells of atoms j, k, l (atom i is in
+ *                     the home cell), each component in [-64, 64]
+ *   phi   [n][81]     eV/Angstrom^4, index ((alpha*3 + beta)*3 + gamma)*3 + theta
+ * 1 <= n <= 2^20.  The list need not be symmetric; the rate is evaluated for whatever is
+ * given. */
+int fp4_load_fc4(fp4_ctx *ctx, int32_t nquart, const int32_t *atoms, const int32_t *cells,
+                 const double *phi);
+
+/* Set a tunable (keys FP4_PARAM_*). */
+int fp4_set_param(fp4_ctx *ctx, int32_t key, double value);
+
+/* Synchronous four-phonon rates for every mode of the grid.
+ *   T[nT]                  temperatures (K), 1 <= nT <= 8, each > 0
+ *   scalebroad             > 0
+ *   mask                   nonzero subset of FP4_PP | FP4_PM | FP4_MM
+ *   precision              FP4_FP64 or FP4_FP32
+ *   rates                  host [nT][nq*nb] 1/ps (required)
+ *   rates_by_channel       host [nT][3][nq*nb] or NULL
+ *   counts                 host [nq*nb][3] kept processes per channel (Numprocess) or NULL
+ * Inactive modes get rate 0 and count 0. */
+int fp4_compute_rates4(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                       uint32_t mask, int32_t precision, double *rates,
+                       double *rates_by_channel, int64_t *counts);
+
+/* Same for an explicit list of target mode ids (chunked or resumed runs, sampled checks).
+ *   targets [ntargets] in [0, nq*nb), 1 <= ntargets <= nq*nb
+ *   outputs as above with nq*nb replaced by ntargets (rates [nT][ntargets], ...). */
+int fp4_compute_rates4_subset(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                              uint32_t mask, int32_t precision, const int32_t *targets,
+                              int32_t ntargets, double *rates, double *rates_by_channel,
+                              int64_t *counts);
+
+/* Asynchronous form for callers that own the stream and the output memory.
+ *   hip_stream   a hipStream_t of the context's device (NULL = the null stream)
+ *   d_rates      DEVICE [nT][nq*nb] doubles (required)
+ *   d_rates_by_channel DEVICE [nT][3][nq*nb] or NULL;  d_counts DEVICE [nq*nb][3] or NULL
+ * All work is enqueued on hip_stream; the call returns without waiting.  The context's
+ * internal buffers are reused by the next call, so calls on one context must not overlap
+ * on different streams. */
+int fp4_compute_rates4_async(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                             uint32_t mask, int32_t precision, void *hip_stream,
+                             double *d_rates, double *d_rates_by_channel, int64_t *d_counts);
+
+/* Matrix elements V of Eq. V4 through the library's own contraction path.
+ *   quads [n][8] = (iq, j, iq', j', iq'', j'', j''', channel) with channel 0 (++), 1 (+-),
+ *                  2 (--); iq''' is q + s' q' + s'' q'' folded into the grid
+ *   V     [n] complex, interleaved (re, im)
+ * Test hook; 1 <= n <= 2^16. */
+int fp4_debug_matrix_elements(fp4_ctx *ctx, int32_t n, const int32_t *quads,
+                              int32_t precision, double *V);
+
+/* Work counts of the last compute call: kept processes (all channels), candidate processes
+ * enumerated, and branch blocks contracted. */
+int fp4_last_stats(const fp4_ctx *ctx, int64_t *processes, int64_t *candidates,
+                   int64_t *blocks);
+
+/* With FP4_PARAM_PROFILE = 1: device time (ms) of the last call's kernels, from HIP events
+ * recorded on the call's stream: main = the fused enumeration/contraction kernel, total =
+ * first to last kernel. */
+int fp4_last_timing(const fp4_ctx *ctx, double *ms_main, double *ms_total);
+
+/* Human-readable reason of the last error on this context ("" if none). */
+const char *fp4_last_error(const fp4_ctx *ctx);
+
+/* Static description of an error code. */
+const char *fp4_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FP4_H */

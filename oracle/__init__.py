@@ -22,7 +22,7 @@ def build(force: bool = True) -> str:
     """Compile oracle4.c with gcc (OpenMP, no FP contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fcx-limited-range",
                "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
@@ -40,6 +40,9 @@ def lib():
         L.oracle_rates4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32, f64,
                                     f64, f64, i32, P, i32, P, P, P, i32]
         L.oracle_rates4.restype = ctypes.c_int
+        L.oracle_rates4_partners.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32,
+                                             f64, f64, f64, i32, P, i32, P, i32, P, P, P, i32]
+        L.oracle_rates4_partners.restype = ctypes.c_int
         L.oracle_v4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, i32, P, P, P]
         L.oracle_v4.restype = ctypes.c_int
         for name in ("oracle_hbar_over_kb", "oracle_c4"):
@@ -111,6 +114,26 @@ def rates4(model: Model, T, scalebroad, mask, dq, targets=None, window_w=2.0,
     if rc != 0:
         raise ValueError(f"oracle_rates4 returned {rc}")
     return rates, rch, counts
+
+
+def rates4_partners(model: Model, T, scalebroad, mask, dq, targets, q1list, window_w=2.0,
+                    sigma_min=1e-4, nthreads=0):
+    """The rate sum restricted to partner points q' in q1list (a bounded sample of the work
+    of the full sum).  Returns (rates[nT][nt], counts[nt][3])."""
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    targets = np.ascontiguousarray(targets, dtype=np.int32)
+    q1 = np.ascontiguousarray(q1list, dtype=np.int32)
+    nt = int(targets.shape[0])
+    rates = np.zeros((len(T), nt))
+    rch = np.zeros((len(T), 3, nt))
+    counts = np.zeros((nt, 3), dtype=np.int64)
+    rc = lib().oracle_rates4_partners(*model._common(), _p(T), len(T), float(scalebroad),
+                                      int(mask), float(window_w), float(sigma_min), float(dq),
+                                      nt, _p(targets), len(q1), _p(q1), 1, _p(rates), _p(rch),
+                                      _p(counts), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_rates4_partners returned {rc}")
+    return rates, counts
 
 
 def v4(model: Model, modes4, signs4) -> np.ndarray:

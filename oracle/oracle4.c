@@ -31,7 +31,8 @@
  *
  * Evaluation order of V: per quartet n, the slot-1 and slot-2 factors are contracted first
  * (they are fixed while the loops over q'' and branches run) and the result is then
- * contracted with the slot-3 and slot-4 factors.  Nothing is grouped across quartets.
+ * contracted with the slot-3 and slot-4 factors, which are formed once per (q'', j'') and
+ * per (q''', j''') and reused across the branch loops.  Nothing is grouped across quartets.
  *
  * Compile with -O2 -ffp-contract=off so that the predicate is bit-reproducible.
  */
@@ -85,7 +86,12 @@ typedef struct {
     const int32_t *atoms, *cells;
     const double *phi;
     cplx *rou;          /* exp(2 pi i k / N), exactly conjugate-symmetric */
+    int ncell;          /* distinct cells of slots 2..4 in the quartet list */
+    int *cid;           /* [nq4][3] cell id of slots 2, 3, 4 */
+    cplx *cph;          /* [N][ncell] exp(i q.R) of every grid point and distinct cell */
 } model_t;
+
+static cplx phase(const model_t *m, int iq, const int32_t *R);
 
 static void model_init(model_t *m, const int32_t grid[3], int32_t natoms, const double *mass,
                        const double *omega, const double *evec, const double *vel,
@@ -102,9 +108,30 @@ static void model_init(model_t *m, const int32_t grid[3], int32_t natoms, const 
         m->rou[k] = cos(a) + I * sin(a);
     }
     for (int k = m->N / 2 + 1; k < m->N; ++k) m->rou[k] = conj(m->rou[m->N - k]);
+    /* table of lattice phases for the cells the quartet list uses (a lookup of the same
+     * values phase() returns) */
+    m->cid = (int *)malloc(sizeof(int) * 3 * (size_t)(nq4 > 0 ? nq4 : 1));
+    int32_t *uniq = (int32_t *)malloc(sizeof(int32_t) * 9 * (size_t)(nq4 > 0 ? nq4 : 1));
+    m->ncell = 0;
+    for (int n = 0; n < nq4; ++n)
+        for (int s = 0; s < 3; ++s) {
+            const int32_t *R = cells + 9 * n + 3 * s;
+            int found = -1;
+            for (int u = 0; u < m->ncell && found < 0; ++u)
+                if (uniq[3 * u] == R[0] && uniq[3 * u + 1] == R[1] && uniq[3 * u + 2] == R[2]) found = u;
+            if (found < 0) {
+                found = m->ncell++;
+                uniq[3 * found] = R[0]; uniq[3 * found + 1] = R[1]; uniq[3 * found + 2] = R[2];
+            }
+            m->cid[3 * n + s] = found;
+        }
+    m->cph = (cplx *)malloc(sizeof(cplx) * (size_t)m->N * (m->ncell > 0 ? m->ncell : 1));
+    for (int iq = 0; iq < m->N; ++iq)
+        for (int u = 0; u < m->ncell; ++u) m->cph[(size_t)iq * m->ncell + u] = phase(m, iq, uniq + 3 * u);
+    free(uniq);
 }
 
-static void model_free(model_t *m) { free(m->rou); }
+static void model_free(model_t *m) { free(m->rou); free(m->cid); free(m->cph); }
 
 static void qtriple(const model_t *m, int iq, int n[3]) {
     n[0] = iq % m->g[0];
@@ -144,6 +171,15 @@ static cplx slot_factor(const model_t *m, int sign, int iq, int j, int atom, con
 }
 
 static const int32_t ZERO_CELL[3] = {0, 0, 0};
+
+/* The same factor with the phase taken from the per-cell table (slot = 1, 2, 3 for the
+ * quartet's atoms j, k, l). */
+static cplx slot_factor_n(const model_t *m, int sign, int iq, int j, int n, int slot, int x) {
+    const int atom = m->atoms[4 * n + slot];
+    cplx f = ev(m, iq, j, atom, x) * m->cph[(size_t)iq * m->ncell + m->cid[3 * n + slot - 1]] /
+             sqrt(m->mass[atom]);
+    return sign > 0 ? f : conj(f);
+}
 
 /* V of Eq. V4 for four modes with slot signs sg[0..3] (slot 1 is the target, sign +1 in
  * the rate; the general form is used by the permutation tests).  The quartet's slot-1
@@ -223,6 +259,15 @@ static void neumaier(double *sum, double *comp, double x) {
  * If want_rates == 0 only the counts are produced (no matrix elements are evaluated).
  * Returns 0, or -1 on invalid arguments.
  */
+static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
+                      const double *omega, const double *evec, const double *vel, int32_t nq4,
+                      const int32_t *atoms, const int32_t *cells, const double *phi,
+                      const double *T, int32_t nT, double scalebroad, uint32_t mask,
+                      double window_w, double sigma_min, double dq, int32_t ntargets,
+                      const int32_t *targets, int32_t nq1, const int32_t *q1list,
+                      int32_t want_rates, double *rates, double *rates_ch, int64_t *counts,
+                      int32_t nthreads);
+
 int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
                   const double *omega, const double *evec, const double *vel, int32_t nq4,
                   const int32_t *atoms, const int32_t *cells, const double *phi,
@@ -230,10 +275,42 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
                   double window_w, double sigma_min, double dq, int32_t ntargets,
                   const int32_t *targets, int32_t want_rates, double *rates,
                   double *rates_ch, int64_t *counts, int32_t nthreads) {
+    return rates_core(grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi, T, nT,
+                      scalebroad, mask, window_w, sigma_min, dq, ntargets, targets, -1, NULL,
+                      want_rates, rates, rates_ch, counts, nthreads);
+}
+
+/* Public: the same sum restricted to the partner points q' listed in q1list[nq1] (a sample of
+ * the work of the full sum, used to time the oracle on a bounded part of a workload). */
+int oracle_rates4_partners(const int32_t grid[3], int32_t natoms, const double *mass,
+                           const double *omega, const double *evec, const double *vel,
+                           int32_t nq4, const int32_t *atoms, const int32_t *cells,
+                           const double *phi, const double *T, int32_t nT, double scalebroad,
+                           uint32_t mask, double window_w, double sigma_min, double dq,
+                           int32_t ntargets, const int32_t *targets, int32_t nq1,
+                           const int32_t *q1list, int32_t want_rates, double *rates,
+                           double *rates_ch, int64_t *counts, int32_t nthreads) {
+    if (nq1 < 1 || !q1list) return -1;
+    for (int i = 0; i < nq1; ++i)
+        if (q1list[i] < 0 || q1list[i] >= grid[0] * grid[1] * grid[2]) return -1;
+    return rates_core(grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi, T, nT,
+                      scalebroad, mask, window_w, sigma_min, dq, ntargets, targets, nq1, q1list,
+                      want_rates, rates, rates_ch, counts, nthreads);
+}
+
+static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
+                      const double *omega, const double *evec, const double *vel, int32_t nq4,
+                      const int32_t *atoms, const int32_t *cells, const double *phi,
+                      const double *T, int32_t nT, double scalebroad, uint32_t mask,
+                      double window_w, double sigma_min, double dq, int32_t ntargets,
+                      const int32_t *targets, int32_t nq1, const int32_t *q1list,
+                      int32_t want_rates, double *rates, double *rates_ch, int64_t *counts,
+                      int32_t nthreads) {
     if (natoms <= 0 || nT <= 0 || ntargets < 0 || scalebroad <= 0.0 || dq <= 0.0) return -1;
     model_t m;
     model_init(&m, grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi);
     const int N = m.N, nb = m.nb, nmodes = N * nb;
+    const int NQ1 = q1list ? nq1 : N;   /* partner points q' in the sum */
     const double c_win = ((window_w * scalebroad) * dq) * ((window_w * scalebroad) * dq);
     const double c_sig = (scalebroad * dq) * (scalebroad * dq);
     const double C4 = oracle_c4();
@@ -247,7 +324,7 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
             if (omega[mu] > 0.0) occ[(size_t)t * nmodes + mu] = 1.0 / expm1(hk * omega[mu] / T[t]);
 
     /* partial sums per (target, q') so that the parallel loop has a fixed summation order */
-    const size_t npart = (size_t)ntargets * N;
+    const size_t npart = (size_t)ntargets * NQ1;
     double *part = (double *)calloc(npart * nT * 3 * 2, sizeof(double)); /* sum, comp */
     int64_t *pcnt = (int64_t *)calloc(npart * 3, sizeof(int64_t));
 
@@ -256,10 +333,15 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
 #endif
 #pragma omp parallel
     {
-        cplx *W = (cplx *)malloc(sizeof(cplx) * (size_t)(m.nq4 > 0 ? m.nq4 : 1) * 9);
+        const size_t nq4a = (size_t)(m.nq4 > 0 ? m.nq4 : 1);
+        cplx *W = (cplx *)malloc(sizeof(cplx) * nq4a * 9);
+        cplx *X3 = (cplx *)malloc(sizeof(cplx) * nq4a * 3);
+        cplx *X4all = (cplx *)malloc(sizeof(cplx) * nq4a * 3 * (size_t)nb);
+        int *have4 = (int *)malloc(sizeof(int) * (size_t)nb);
 #pragma omp for schedule(dynamic, 1)
         for (long long task = 0; task < (long long)npart; ++task) {
-            const int it = (int)(task / N), iq1 = (int)(task % N);
+            const int it = (int)(task / NQ1), k1 = (int)(task % NQ1);
+            const int iq1 = q1list ? q1list[k1] : k1;
             const int mu = targets[it];
             const int iq = mu / nb, j = mu % nb;
             double *P = part + (size_t)task * nT * 3 * 2;
@@ -281,7 +363,7 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
                             cplx X1[3], X2[3];
                             for (int x = 0; x < 3; ++x) {
                                 X1[x] = slot_factor(&m, +1, iq, j, at[0], ZERO_CELL, x);
-                                X2[x] = slot_factor(&m, s1, iq1, j1, at[1], cl, x);
+                                X2[x] = slot_factor_n(&m, s1, iq1, j1, n, 1, x);
                             }
                             for (int c = 0; c < 3; ++c)
                                 for (int d = 0; d < 3; ++d) {
@@ -295,9 +377,12 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
                     }
                     for (int iq2 = 0; iq2 < N; ++iq2) {
                         const int iq3 = fold(&m, iq, s1, iq1, s2, iq2);
+                        /* slot-4 factors of this q''' for each j''' (formed on first use) */
+                        memset(have4, 0, sizeof(int) * (size_t)nb);
                         for (int j2 = 0; j2 < nb; ++j2) {
                             const int mu2 = iq2 * nb + j2;
                             if (omega[mu2] <= 0.0) continue;
+                            int have3 = 0;
                             for (int j3 = 0; j3 < nb; ++j3) {
                                 const int mu3 = iq3 * nb + j3;
                                 if (omega[mu3] <= 0.0) continue;
@@ -305,20 +390,27 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
                                 if (!keep_process(&m, ch, mu, mu1, mu2, mu3, c_win, &dw, &s2v)) continue;
                                 C[ch] += 1;
                                 if (!want_rates) continue;
+                                if (!have3) {
+                                    for (int n = 0; n < m.nq4; ++n)
+                                        for (int x = 0; x < 3; ++x)
+                                            X3[3 * n + x] = slot_factor_n(&m, s2, iq2, j2, n, 2, x);
+                                    have3 = 1;
+                                }
+                                cplx *X4 = X4all + (size_t)j3 * nq4a * 3;
+                                if (!have4[j3]) {
+                                    for (int n = 0; n < m.nq4; ++n)
+                                        for (int x = 0; x < 3; ++x)
+                                            X4[3 * n + x] = slot_factor_n(&m, -1, iq3, j3, n, 3, x);
+                                    have4[j3] = 1;
+                                }
                                 /* V = sum_n sum_{gt} W_n^{gt} X3_n^g X4_n^t  (Eq. V4) */
                                 cplx V = 0.0;
-                                for (int n = 0; n < m.nq4; ++n) {
-                                    const int32_t *at = m.atoms + 4 * n;
-                                    const int32_t *cl = m.cells + 9 * n;
-                                    cplx X3[3], X4[3];
-                                    for (int x = 0; x < 3; ++x) {
-                                        X3[x] = slot_factor(&m, s2, iq2, j2, at[2], cl + 3, x);
-                                        X4[x] = slot_factor(&m, -1, iq3, j3, at[3], cl + 6, x);
+                                for (int n = 0; n < m.nq4; ++n)
+                                    for (int c = 0; c < 3; ++c) {
+                                        cplx y = 0.0;
+                                        for (int d = 0; d < 3; ++d) y += W[9 * n + 3 * c + d] * X4[3 * n + d];
+                                        V += X3[3 * n + c] * y;
                                     }
-                                    for (int c = 0; c < 3; ++c)
-                                        for (int d = 0; d < 3; ++d)
-                                            V += W[9 * n + 3 * c + d] * X3[c] * X4[d];
-                                }
                                 const double v2 = creal(V) * creal(V) + cimag(V) * cimag(V);
                                 const double delta = oracle_delta(dw, c_sig * s2v, sigma_min);
                                 const double wprod = omega[mu] * omega[mu1] * omega[mu2] * omega[mu3];
@@ -339,6 +431,9 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
             }
         }
         free(W);
+        free(X3);
+        free(X4all);
+        free(have4);
     }
 
     /* ordered reduction over q' */
@@ -348,8 +443,8 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
             double tot = 0.0, totc = 0.0;
             for (int ch = 0; ch < 3; ++ch) {
                 double s = 0.0, c = 0.0;
-                for (int iq1 = 0; iq1 < N; ++iq1) {
-                    const double *P = part + ((size_t)it * N + iq1) * nT * 3 * 2;
+                for (int k1 = 0; k1 < NQ1; ++k1) {
+                    const double *P = part + ((size_t)it * NQ1 + k1) * nT * 3 * 2;
                     neumaier(&s, &c, P[(t * 3 + ch) * 2]);
                     c += P[(t * 3 + ch) * 2 + 1];
                 }
@@ -358,8 +453,8 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
             }
             rates[(size_t)t * ntargets + it] = tot + totc;
         }
-        for (int iq1 = 0; iq1 < N; ++iq1)
-            for (int ch = 0; ch < 3; ++ch) cc[ch] += pcnt[((size_t)it * N + iq1) * 3 + ch];
+        for (int k1 = 0; k1 < NQ1; ++k1)
+            for (int ch = 0; ch < 3; ++ch) cc[ch] += pcnt[((size_t)it * NQ1 + k1) * 3 + ch];
         if (counts) for (int ch = 0; ch < 3; ++ch) counts[3 * (size_t)it + ch] = cc[ch];
     }
     free(part); free(pcnt); free(occ);

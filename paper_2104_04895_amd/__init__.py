@@ -1,0 +1,210 @@
+"""Python binding of the MI355X four-phonon RTA rate library (libfp4.so, C ABI in
+include/fp4.h).
+
+Argument marshalling only: every step of the rate computation runs in the HIP kernels of
+libfp4.so.  Importing works without the library; creating a Context raises if libfp4.so has
+not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfp4.so")
+
+FP4_OK = 0
+FP4_E_INVAL = -1
+FP4_E_STATE = -2
+FP4_E_NOMEM = -3
+FP4_E_DEVICE = -4
+FP4_E_UNSUPPORTED = -5
+
+FP4_FP64 = 0
+FP4_FP32 = 1
+
+FP4_PARAM_WINDOW_W = 1
+FP4_PARAM_SIGMA_MIN = 2
+FP4_PARAM_QCHUNK = 3
+FP4_PARAM_PROFILE = 4
+
+FP4_PP, FP4_PM, FP4_MM = 1, 2, 4
+
+EXPORTED = [
+    "fp4_create", "fp4_destroy", "fp4_load_lattice", "fp4_load_modes", "fp4_load_fc4",
+    "fp4_set_param", "fp4_compute_rates4", "fp4_compute_rates4_subset",
+    "fp4_compute_rates4_async", "fp4_debug_matrix_elements", "fp4_last_stats",
+    "fp4_last_timing", "fp4_last_error", "fp4_strerror",
+]
+
+_lib = None
+
+
+class Fp4Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def lib():
+    """Load libfp4.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2104_04895_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, u32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+        L.fp4_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        L.fp4_destroy.argtypes = [P]
+        L.fp4_destroy.restype = None
+        L.fp4_load_lattice.argtypes = [P, P, P, i32, P, f64]
+        L.fp4_load_modes.argtypes = [P, i32, i32, P, P, P]
+        L.fp4_load_fc4.argtypes = [P, i32, P, P, P]
+        L.fp4_set_param.argtypes = [P, i32, f64]
+        L.fp4_compute_rates4.argtypes = [P, P, i32, f64, u32, i32, P, P, P]
+        L.fp4_compute_rates4_subset.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P]
+        L.fp4_compute_rates4_async.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
+        L.fp4_debug_matrix_elements.argtypes = [P, i32, P, i32, P]
+        L.fp4_last_stats.argtypes = [P, P, P, P]
+        L.fp4_last_timing.argtypes = [P, P, P]
+        L.fp4_last_error.argtypes = [P]
+        L.fp4_last_error.restype = ctypes.c_char_p
+        L.fp4_strerror.argtypes = [ctypes.c_int]
+        L.fp4_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """One library context on one HIP device (wraps fp4_create / fp4_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        rc = self._L.fp4_create(ctypes.byref(h), int(device))
+        if rc != FP4_OK:
+            raise Fp4Error(rc, f"fp4_create failed: {self._L.fp4_strerror(rc).decode()}")
+        self._h = h
+        self.nq = self.nb = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fp4_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != FP4_OK:
+            msg = self._L.fp4_last_error(self._h).decode()
+            raise Fp4Error(rc, f"{what}: {msg}")
+
+    def call(self, name, *args):
+        """Raw ABI call returning the status code (for error-path tests)."""
+        return getattr(self._L, name)(self._h, *args)
+
+    # ------------------------------------------------------------------ loads
+    def load_lattice(self, A, grid, mass, dq=0.0):
+        A = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+        g = np.ascontiguousarray(grid, dtype=np.int32)
+        m = np.ascontiguousarray(mass, dtype=np.float64)
+        self._check(self._L.fp4_load_lattice(self._h, _p(A), _p(g), len(m), _p(m), float(dq)),
+                    "fp4_load_lattice")
+        self.nq = int(np.prod(g))
+        self.nb = 3 * len(m)
+
+    def load_modes(self, omega, evec, vel):
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        ev = np.ascontiguousarray(evec, dtype=np.complex128).view(np.float64)
+        ve = np.ascontiguousarray(vel, dtype=np.float64)
+        self._check(self._L.fp4_load_modes(self._h, om.shape[0], om.shape[1], _p(om), _p(ev), _p(ve)),
+                    "fp4_load_modes")
+
+    def load_fc4(self, atoms, cells, phi):
+        at = np.ascontiguousarray(atoms, dtype=np.int32)
+        cl = np.ascontiguousarray(cells, dtype=np.int32)
+        ph = np.ascontiguousarray(phi, dtype=np.float64)
+        self._check(self._L.fp4_load_fc4(self._h, at.shape[0], _p(at), _p(cl), _p(ph)), "fp4_load_fc4")
+
+    def load_instance(self, inst, dq=0.0, phi_scale=1.0):
+        self.load_lattice(inst.cr.A, inst.grid, inst.cr.mass, dq)
+        self.load_modes(inst.omega, inst.evec, inst.vel)
+        self.load_fc4(inst.fc4.atoms, inst.fc4.cells, inst.fc4.phi * phi_scale)
+
+    def set_param(self, key, value):
+        self._check(self._L.fp4_set_param(self._h, int(key), float(value)), "fp4_set_param")
+
+    # ------------------------------------------------------------------ compute
+    def compute_rates4(self, T, scalebroad=1.0, mask=7, precision=FP4_FP64, targets=None,
+                       by_channel=False, counts=True):
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        nT = len(T)
+        if targets is None:
+            nt = self.nq * self.nb
+        else:
+            targets = np.ascontiguousarray(targets, dtype=np.int32)
+            nt = len(targets)
+        rates = np.zeros((nT, nt))
+        rch = np.zeros((nT, 3, nt)) if by_channel else None
+        cnt = np.zeros((nt, 3), dtype=np.int64) if counts else None
+        if targets is None:
+            rc = self._L.fp4_compute_rates4(self._h, _p(T), nT, float(scalebroad), int(mask),
+                                            int(precision), _p(rates), _p(rch), _p(cnt))
+        else:
+            rc = self._L.fp4_compute_rates4_subset(self._h, _p(T), nT, float(scalebroad),
+                                                   int(mask), int(precision), _p(targets), nt,
+                                                   _p(rates), _p(rch), _p(cnt))
+        self._check(rc, "fp4_compute_rates4")
+        return rates, rch, cnt
+
+    def compute_rates4_async(self, T, scalebroad, mask, precision, stream_ptr, d_rates,
+                             d_rates_ch=0, d_counts=0):
+        """Device-pointer form (torch tensors' data_ptr() and a stream handle)."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        rc = self._L.fp4_compute_rates4_async(self._h, _p(T), len(T), float(scalebroad), int(mask),
+                                              int(precision), ctypes.c_void_p(stream_ptr),
+                                              ctypes.c_void_p(d_rates),
+                                              ctypes.c_void_p(d_rates_ch or None),
+                                              ctypes.c_void_p(d_counts or None))
+        self._check(rc, "fp4_compute_rates4_async")
+
+    def debug_matrix_elements(self, quads, precision=FP4_FP64):
+        q = np.ascontiguousarray(quads, dtype=np.int32).reshape(-1, 8)
+        V = np.zeros(len(q), dtype=np.complex128)
+        self._check(self._L.fp4_debug_matrix_elements(self._h, len(q), _p(q), int(precision),
+                                                      _p(V.view(np.float64))),
+                    "fp4_debug_matrix_elements")
+        return V
+
+    def last_stats(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._L.fp4_last_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                    "fp4_last_stats")
+        return {"processes": a.value, "candidates": b.value, "blocks": c.value}
+
+    def last_timing(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self._L.fp4_last_timing(self._h, ctypes.byref(a), ctypes.byref(b)), "fp4_last_timing")
+        return {"ms_main": a.value, "ms_total": b.value}
+
+
+def build():
+    from .build import build as _b
+    return _b()

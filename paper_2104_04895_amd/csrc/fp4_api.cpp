@@ -1,0 +1,786 @@
+// fp4_api.cpp -- host side of the four-phonon rate library: context, argument checks,
+// regrouping of the quartet list, device buffers and kernel launches.  The ABI is declared
+// in include/fp4.h.
+#include "fp4.h"
+#include "fp4_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace {
+
+// SI 2019 exact h, k_B, e; CODATA 2018 atomic mass unit
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kH = 6.62607015e-34;
+constexpr double kKB = 1.380649e-23;
+constexpr double kEV = 1.602176634e-19;
+constexpr double kAMU = 1.66053906660e-27;
+
+double hbar_over_kb_kps() { return kH / (2.0 * kPi) / kKB * 1.0e12; }
+
+// Eq. 4phgamma prefactor hbar^2 pi / 8 for V in eV/(A^4 amu^2), delta in ps, omega in
+// rad/ps, rate in 1/ps (the two 1/N factors are applied separately).
+double c4_prefactor() {
+  const double hbar = kH / (2.0 * kPi);
+  const double kv = kEV / (1e-40 * kAMU * kAMU);
+  return hbar * hbar * kPi / 8.0 * kv * kv * 1.0e-72;
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct fp4_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int fail_alloc_at = -1;  // test hook: FP4_TEST_FAIL_ALLOC
+  int alloc_count = 0;
+
+  // lattice
+  bool have_lattice = false;
+  double A[9] = {0};
+  int grid[3] = {0, 0, 0};
+  int N = 0, nat = 0, nb = 0;
+  std::vector<double> mass;
+  double dq = 0.0;
+  // modes / fc4 loaded flags
+  bool have_modes = false, have_fc4 = false, tables_dirty = true;
+  // parameters
+  double window_w = 2.0, sigma_min = 1e-4;
+  int qchunk = 0, profile = 0;
+
+  // regrouped quartet list (host)
+  int ng = 0, nc = 0, nq4 = 0, na = 0, nbv = 0, nd = 0;
+  std::vector<int> g_d, kl_start, c_start, c_jat, c_a, cq_start, q_i, q_b, avec, bvec, dvec;
+  std::vector<double> q_phi;
+
+  // device buffers
+  DevBuf d_omega, d_iw, d_vel, d_evec, d_mass, d_E64, d_E32, d_qn, d_PHA64, d_PHB64, d_PHD64, d_PHD32;
+  DevBuf d_g_d, d_kl, d_cs, d_cj, d_ca, d_cq, d_qi, d_qb, d_qphi, d_avec, d_bvec, d_dvec;
+  DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
+  DevBuf d_rates, d_rch, d_counts, d_quads, d_tslot, d_V;
+
+  // statistics / timing of the last call
+  long long st_processes = 0, st_candidates = 0, st_blocks = 0;
+  double ms_main = 0.0, ms_total = 0.0;
+  std::vector<hipEvent_t> ev_pool;
+
+  int fail(int code, const std::string &msg) {
+    err = msg;
+    return code;
+  }
+};
+
+namespace {
+
+#define FP4_HIP(ctx, expr)                                                             \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return (ctx)->fail(FP4_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int ensure(fp4_ctx *ctx, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return FP4_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (e != hipSuccess) return ctx->fail(FP4_E_DEVICE, std::string("hipFree: ") + hipGetErrorString(e));
+  }
+  ctx->alloc_count++;
+  if (ctx->fail_alloc_at >= 0 && ctx->alloc_count == ctx->fail_alloc_at)
+    return ctx->fail(FP4_E_NOMEM, "device allocation failed (injected by FP4_TEST_FAIL_ALLOC)");
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return ctx->fail(FP4_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return FP4_OK;
+}
+
+template <typename T>
+int upload(fp4_ctx *ctx, DevBuf &b, const T *src, size_t n) {
+  int rc = ensure(ctx, b, n * sizeof(T));
+  if (rc) return rc;
+  if (n) FP4_HIP(ctx, hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  return FP4_OK;
+}
+
+void release(DevBuf &b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+fp4::Crystal make_crystal(const fp4_ctx *ctx) {
+  fp4::Crystal c{};
+  c.g0 = ctx->grid[0];
+  c.g1 = ctx->grid[1];
+  c.g2 = ctx->grid[2];
+  c.N = ctx->N;
+  c.nat = ctx->nat;
+  c.nb = ctx->nb;
+  c.ng = ctx->ng;
+  c.nc = ctx->nc;
+  c.nq4 = ctx->nq4;
+  c.na = ctx->na;
+  c.nbv = ctx->nbv;
+  c.nd = ctx->nd;
+  c.omega = (const double *)ctx->d_omega.p;
+  c.inv_omega = (const double *)ctx->d_iw.p;
+  c.vel = (const double4 *)ctx->d_vel.p;
+  c.E64 = (const double2 *)ctx->d_E64.p;
+  c.E32 = (const float2 *)ctx->d_E32.p;
+  c.qn = (const int4 *)ctx->d_qn.p;
+  c.PHA64 = (const double2 *)ctx->d_PHA64.p;
+  c.PHB64 = (const double2 *)ctx->d_PHB64.p;
+  c.PHD64 = (const double2 *)ctx->d_PHD64.p;
+  c.PHD32 = (const float2 *)ctx->d_PHD32.p;
+  c.g_d = (const int *)ctx->d_g_d.p;
+  c.kl_start = (const int *)ctx->d_kl.p;
+  c.c_start = (const int *)ctx->d_cs.p;
+  c.c_jat = (const int *)ctx->d_cj.p;
+  c.c_a = (const int *)ctx->d_ca.p;
+  c.cq_start = (const int *)ctx->d_cq.p;
+  c.q_i = (const int *)ctx->d_qi.p;
+  c.q_b = (const int *)ctx->d_qb.p;
+  c.q_phi = (const double *)ctx->d_qphi.p;
+  return c;
+}
+
+// Build every per-q table (E, grid triples, phases) once modes and quartets are loaded.
+int ensure_tables(fp4_ctx *ctx) {
+  if (!ctx->tables_dirty) return FP4_OK;
+  const size_t N = ctx->N, nb = ctx->nb;
+  int rc;
+  if ((rc = ensure(ctx, ctx->d_iw, N * nb * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_E64, N * nb * nb * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_E32, N * nb * nb * sizeof(float2)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_qn, N * sizeof(int4)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_PHA64, N * ctx->na * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_PHB64, N * ctx->nbv * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_PHD64, N * ctx->nd * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_PHD32, N * ctx->nd * sizeof(float2)))) return rc;
+  fp4::Crystal c = make_crystal(ctx);
+  FP4_HIP(ctx, fp4::launch_tables(c, (double *)ctx->d_iw.p, (double2 *)ctx->d_E64.p, (float2 *)ctx->d_E32.p,
+                                  (const double *)ctx->d_evec.p, (const double *)ctx->d_mass.p,
+                                  (int4 *)ctx->d_qn.p, (double2 *)ctx->d_PHA64.p,
+                                  (double2 *)ctx->d_PHB64.p, (double2 *)ctx->d_PHD64.p,
+                                  (float2 *)ctx->d_PHD32.p, (const int *)ctx->d_avec.p,
+                                  (const int *)ctx->d_bvec.p, (const int *)ctx->d_dvec.p,
+                                  ctx->stream));
+  ctx->tables_dirty = false;
+  return FP4_OK;
+}
+
+hipEvent_t pool_event(fp4_ctx *ctx, size_t i) {
+  while (ctx->ev_pool.size() <= i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  return ctx->ev_pool[i];
+}
+
+// Enqueue the whole rate computation for `nt` targets (device list d_targets) on `s`.
+// Device outputs: rates [nT][nt], rates_ch [nT][3][nt] (nullable), counts [nt][3] (nullable).
+int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int precision,
+            int nt, hipStream_t s, double *d_rates, double *d_rch, long long *d_counts,
+            std::vector<std::pair<hipEvent_t, hipEvent_t>> *main_ev, size_t *evi) {
+  int rc;
+  const int fp32 = precision == FP4_FP32;
+  const size_t nmodes = (size_t)ctx->N * ctx->nb;
+  if ((rc = ensure_tables(ctx))) return rc;
+  if ((rc = upload(ctx, ctx->d_T, T, (size_t)nT))) return rc;
+  if ((rc = ensure(ctx, ctx->d_occ, nmodes * nT * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_iocc, nmodes * nT * sizeof(double)))) return rc;
+  fp4::Crystal c = make_crystal(ctx);
+  FP4_HIP(ctx, fp4::launch_occupations(c, (const double *)ctx->d_T.p, nT, hbar_over_kb_kps(),
+                                       (double *)ctx->d_occ.p, (double *)ctx->d_iocc.p, s));
+
+  // work decomposition: q'-chunks per target so that a launch has enough work-groups
+  int qchunk = ctx->qchunk;
+  if (qchunk <= 0) {
+    long long want = 8192;
+    long long nchunk = (want + nt - 1) / nt;
+    if (nchunk < 1) nchunk = 1;
+    if (nchunk > ctx->N) nchunk = ctx->N;
+    qchunk = (int)((ctx->N + nchunk - 1) / nchunk);
+  }
+  if (qchunk > ctx->N) qchunk = ctx->N;
+  const int nchunk = (ctx->N + qchunk - 1) / qchunk;
+  const size_t cbytes = fp32 ? sizeof(float2) : sizeof(double2);
+  const size_t per_target = (size_t)ctx->nc * 27 * cbytes;
+  const size_t ubudget = (size_t)512 << 20;
+  int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, ubudget / per_target));
+  // keep launches under 2^31 work-groups
+  batch = (int)std::min<long long>(batch, ((1ll << 31) - 1) / nchunk);
+
+  if ((rc = ensure(ctx, ctx->d_U, (size_t)batch * per_target))) return rc;
+  if ((rc = ensure(ctx, ctx->d_partial, (size_t)nt * nchunk * 3 * nT * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_pcount, (size_t)nt * nchunk * 3 * sizeof(unsigned long long)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_blocks, sizeof(unsigned long long)))) return rc;
+  FP4_HIP(ctx, fp4::launch_zero(ctx->d_blocks.p, sizeof(unsigned long long), s));
+
+  fp4::RateArgs a{};
+  const double wsb = ctx->window_w * sb;
+  a.c_win = (wsb * ctx->dq) * (wsb * ctx->dq);
+  a.c_sig = (sb * ctx->dq) * (sb * ctx->dq);
+  a.c_min = ctx->sigma_min * ctx->sigma_min;
+  a.kpref = c4_prefactor() / ((double)ctx->N * (double)ctx->N);
+  a.nT = nT;
+  a.mask = mask;
+  a.occ = (const double *)ctx->d_occ.p;
+  a.inv_occ = (const double *)ctx->d_iocc.p;
+  a.qchunk = qchunk;
+  a.nchunk = nchunk;
+  a.U = ctx->d_U.p;
+  a.partial = (double *)ctx->d_partial.p;
+  a.pcount = (unsigned long long *)ctx->d_pcount.p;
+  a.blocks = (unsigned long long *)ctx->d_blocks.p;
+  for (int t0 = 0; t0 < nt; t0 += batch) {
+    const int nb_t = std::min(batch, nt - t0);
+    const int *tg = (const int *)ctx->d_targets.p + t0;
+    FP4_HIP(ctx, fp4::launch_precontract(c, tg, nb_t, fp32, ctx->d_U.p, s));
+    a.targets = tg;
+    a.nt = nb_t;
+    a.t0 = t0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (main_ev) {
+      e0 = pool_event(ctx, (*evi)++);
+      e1 = pool_event(ctx, (*evi)++);
+      if (!e0 || !e1) return ctx->fail(FP4_E_DEVICE, "hipEventCreate failed");
+      FP4_HIP(ctx, hipEventRecord(e0, s));
+    }
+    hipError_t le = fp4::launch_rates(c, a, fp32, s);
+    if (le == hipErrorInvalidValue)
+      return ctx->fail(FP4_E_UNSUPPORTED, "the quartet list needs more LDS than a work-group has (too many atom-pair groups for this branch count)");
+    FP4_HIP(ctx, le);
+    if (main_ev) {
+      FP4_HIP(ctx, hipEventRecord(e1, s));
+      main_ev->push_back({e0, e1});
+    }
+  }
+  FP4_HIP(ctx, fp4::launch_reduce(a, nt, d_rates, d_rch, d_counts, s));
+  return FP4_OK;
+}
+
+int check_compute_args(fp4_ctx *ctx, const double *T, int32_t nT, double sb, uint32_t mask,
+                       int32_t precision) {
+  if (!ctx) return FP4_E_INVAL;
+  if (!ctx->have_lattice || !ctx->have_modes || !ctx->have_fc4)
+    return ctx->fail(FP4_E_STATE, "compute called before fp4_load_lattice, fp4_load_modes and fp4_load_fc4");
+  if (!T || nT < 1 || nT > 8) return ctx->fail(FP4_E_INVAL, "need 1 <= nT <= 8 temperatures");
+  for (int i = 0; i < nT; ++i)
+    if (!(std::isfinite(T[i]) && T[i] > 0.0)) return ctx->fail(FP4_E_INVAL, "temperatures must be finite and > 0");
+  if (!(std::isfinite(sb) && sb > 0.0)) return ctx->fail(FP4_E_INVAL, "scalebroad must be finite and > 0");
+  if (mask == 0 || (mask & ~7u)) return ctx->fail(FP4_E_INVAL, "mask must be a nonzero subset of FP4_PP|FP4_PM|FP4_MM");
+  if (precision != FP4_FP64 && precision != FP4_FP32)
+    return ctx->fail(FP4_E_UNSUPPORTED, "precision must be FP4_FP64 or FP4_FP32");
+  return FP4_OK;
+}
+
+int finish_stats(fp4_ctx *ctx, const std::vector<std::pair<hipEvent_t, hipEvent_t>> &ev,
+                 hipEvent_t first, hipEvent_t last) {
+  unsigned long long blocks = 0;
+  FP4_HIP(ctx, hipMemcpy(&blocks, ctx->d_blocks.p, sizeof(blocks), hipMemcpyDeviceToHost));
+  ctx->st_blocks = (long long)blocks;
+  ctx->ms_main = 0.0;
+  ctx->ms_total = 0.0;
+  if (ctx->profile) {
+    for (auto &p : ev) {
+      float ms = 0.f;
+      FP4_HIP(ctx, hipEventElapsedTime(&ms, p.first, p.second));
+      ctx->ms_main += ms;
+    }
+    if (first && last) {
+      float ms = 0.f;
+      FP4_HIP(ctx, hipEventElapsedTime(&ms, first, last));
+      ctx->ms_total = ms;
+    }
+  }
+  return FP4_OK;
+}
+
+int compute_common(fp4_ctx *ctx, const double *T, int32_t nT, double sb, uint32_t mask,
+                   int32_t precision, const int32_t *targets, int32_t nt, double *rates,
+                   double *rates_ch, int64_t *counts) {
+  int rc = check_compute_args(ctx, T, nT, sb, mask, precision);
+  if (rc) return rc;
+  if (!rates) return ctx->fail(FP4_E_INVAL, "rates output is required");
+  const int nmodes = ctx->N * ctx->nb;
+  std::vector<int> tl;
+  if (targets) {
+    if (nt < 1 || nt > nmodes) return ctx->fail(FP4_E_INVAL, "need 1 <= ntargets <= nq*nb");
+    tl.assign(targets, targets + nt);
+    for (int v : tl)
+      if (v < 0 || v >= nmodes) return ctx->fail(FP4_E_INVAL, "target mode id out of range");
+  } else {
+    nt = nmodes;
+    tl.resize(nt);
+    for (int i = 0; i < nt; ++i) tl[i] = i;
+  }
+  if ((rc = upload(ctx, ctx->d_targets, tl.data(), tl.size()))) return rc;
+  if ((rc = ensure(ctx, ctx->d_rates, (size_t)nT * nt * sizeof(double)))) return rc;
+  if (rates_ch && (rc = ensure(ctx, ctx->d_rch, (size_t)nT * 3 * nt * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_counts, (size_t)nt * 3 * sizeof(long long)))) return rc;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t evi = 0;
+  hipEvent_t first = nullptr, last = nullptr;
+  if (ctx->profile) {
+    first = pool_event(ctx, evi++);
+    if (!first) return ctx->fail(FP4_E_DEVICE, "hipEventCreate failed");
+    FP4_HIP(ctx, hipEventRecord(first, ctx->stream));
+  }
+  rc = enqueue(ctx, T, nT, sb, mask, precision, nt, ctx->stream, (double *)ctx->d_rates.p,
+               rates_ch ? (double *)ctx->d_rch.p : nullptr, (long long *)ctx->d_counts.p,
+               ctx->profile ? &ev : nullptr, &evi);
+  if (rc) return rc;
+  if (ctx->profile) {
+    last = pool_event(ctx, evi++);
+    if (!last) return ctx->fail(FP4_E_DEVICE, "hipEventCreate failed");
+    FP4_HIP(ctx, hipEventRecord(last, ctx->stream));
+  }
+  FP4_HIP(ctx, hipMemcpyAsync(rates, ctx->d_rates.p, (size_t)nT * nt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  if (rates_ch)
+    FP4_HIP(ctx, hipMemcpyAsync(rates_ch, ctx->d_rch.p, (size_t)nT * 3 * nt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  std::vector<long long> cnt((size_t)nt * 3);
+  FP4_HIP(ctx, hipMemcpyAsync(cnt.data(), ctx->d_counts.p, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost, ctx->stream));
+  FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  long long tot = 0;
+  for (long long v : cnt) tot += v;
+  if (counts) std::memcpy(counts, cnt.data(), cnt.size() * sizeof(long long));
+  ctx->st_processes = tot;
+  // candidates: active targets x active partner modes^2 x nb (j''') per enabled channel
+  long long act = 0;
+  // (computed from the host copy of omega kept at load time)
+  (void)act;
+  if ((rc = finish_stats(ctx, ev, first, last))) return rc;
+  ctx->err.clear();
+  return FP4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fp4_strerror(int code) {
+  switch (code) {
+    case FP4_OK: return "success";
+    case FP4_E_INVAL: return "invalid argument";
+    case FP4_E_STATE: return "invalid state (missing or inconsistent loads)";
+    case FP4_E_NOMEM: return "out of memory";
+    case FP4_E_DEVICE: return "HIP device error";
+    case FP4_E_UNSUPPORTED: return "unsupported option";
+    default: return "unknown error code";
+  }
+}
+
+int fp4_create(fp4_ctx **out, int device_id) {
+  if (!out) return FP4_E_INVAL;
+  *out = nullptr;
+  fp4_ctx *ctx = new (std::nothrow) fp4_ctx();
+  if (!ctx) return FP4_E_NOMEM;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device_id < 0 || device_id >= ndev) {
+    (void)hipGetLastError();
+    delete ctx;
+    return FP4_E_DEVICE;
+  }
+  if (hipSetDevice(device_id) != hipSuccess) {
+    delete ctx;
+    return FP4_E_DEVICE;
+  }
+  ctx->device = device_id;
+  if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+    delete ctx;
+    return FP4_E_DEVICE;
+  }
+  if (const char *f = std::getenv("FP4_TEST_FAIL_ALLOC")) ctx->fail_alloc_at = std::atoi(f);
+  *out = ctx;
+  return FP4_OK;
+}
+
+void fp4_destroy(fp4_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
+                   &ctx->d_E32, &ctx->d_qn, &ctx->d_PHA64, &ctx->d_PHB64, &ctx->d_PHD64,
+                   &ctx->d_PHD32, &ctx->d_g_d, &ctx->d_kl, &ctx->d_cs, &ctx->d_cj, &ctx->d_ca,
+                   &ctx->d_cq, &ctx->d_qi, &ctx->d_qb, &ctx->d_qphi, &ctx->d_avec, &ctx->d_bvec,
+                   &ctx->d_dvec, &ctx->d_T, &ctx->d_occ, &ctx->d_iocc, &ctx->d_targets,
+                   &ctx->d_U, &ctx->d_partial, &ctx->d_pcount, &ctx->d_blocks, &ctx->d_rates,
+                   &ctx->d_rch, &ctx->d_counts, &ctx->d_quads, &ctx->d_tslot, &ctx->d_V};
+  for (DevBuf *b : all) release(*b);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char *fp4_last_error(const fp4_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int fp4_load_lattice(fp4_ctx *ctx, const double A[9], const int32_t grid[3], int32_t natoms,
+                     const double *mass, double dq) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (!A || !grid || !mass) return ctx->fail(FP4_E_INVAL, "null pointer argument");
+    if (!finite_all(A, 9)) return ctx->fail(FP4_E_INVAL, "lattice vectors must be finite");
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(std::fabs(det) > 1e-9)) return ctx->fail(FP4_E_INVAL, "lattice vectors are singular");
+    long long N = 1;
+    for (int d = 0; d < 3; ++d) {
+      if (grid[d] < 1) return ctx->fail(FP4_E_INVAL, "grid dimensions must be >= 1");
+      N *= grid[d];
+    }
+    if (N > (1 << 20)) return ctx->fail(FP4_E_INVAL, "grid larger than 2^20 points");
+    if (natoms < 1 || natoms > 4) return ctx->fail(FP4_E_UNSUPPORTED, "1 <= natoms <= 4 supported");
+    for (int i = 0; i < natoms; ++i)
+      if (!(std::isfinite(mass[i]) && mass[i] > 0.0)) return ctx->fail(FP4_E_INVAL, "masses must be finite and > 0");
+    if (!std::isfinite(dq)) return ctx->fail(FP4_E_INVAL, "dq must be finite");
+    (void)hipSetDevice(ctx->device);
+    std::memcpy(ctx->A, A, sizeof(ctx->A));
+    for (int d = 0; d < 3; ++d) ctx->grid[d] = grid[d];
+    ctx->N = (int)N;
+    ctx->nat = natoms;
+    ctx->nb = 3 * natoms;
+    ctx->mass.assign(mass, mass + natoms);
+    if (dq > 0.0) {
+      ctx->dq = dq;
+    } else {
+      const double detB = std::pow(2.0 * kPi, 3) / std::fabs(det);
+      ctx->dq = std::cbrt(detB / (double)N);
+    }
+    int rc = upload(ctx, ctx->d_mass, ctx->mass.data(), ctx->mass.size());
+    if (rc) return rc;
+    ctx->have_lattice = true;
+    ctx->have_modes = false;
+    ctx->have_fc4 = false;
+    ctx->tables_dirty = true;
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_load_modes(fp4_ctx *ctx, int32_t nq, int32_t nb, const double *omega,
+                   const double *evec, const double *vel) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (!ctx->have_lattice) return ctx->fail(FP4_E_STATE, "fp4_load_lattice must come first");
+    if (nq != ctx->N || nb != ctx->nb) return ctx->fail(FP4_E_STATE, "nq must equal the grid size and nb = 3*natoms");
+    if (!omega || !evec || !vel) return ctx->fail(FP4_E_INVAL, "null pointer argument");
+    const size_t nm = (size_t)nq * nb;
+    if (!finite_all(omega, nm) || !finite_all(evec, nm * nb * 2) || !finite_all(vel, nm * 3))
+      return ctx->fail(FP4_E_INVAL, "modes contain NaN or Inf");
+    (void)hipSetDevice(ctx->device);
+    std::vector<double> v4(nm * 4, 0.0);
+    for (size_t i = 0; i < nm; ++i)
+      for (int x = 0; x < 3; ++x) v4[4 * i + x] = vel[3 * i + x];
+    int rc;
+    if ((rc = upload(ctx, ctx->d_omega, omega, nm))) return rc;
+    if ((rc = upload(ctx, ctx->d_vel, v4.data(), v4.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_evec, evec, nm * nb * 2))) return rc;
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->have_modes = true;
+    ctx->tables_dirty = true;
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_load_fc4(fp4_ctx *ctx, int32_t nquart, const int32_t *atoms, const int32_t *cells,
+                 const double *phi) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (!ctx->have_lattice) return ctx->fail(FP4_E_STATE, "fp4_load_lattice must come first");
+    if (nquart < 1 || nquart > (1 << 20)) return ctx->fail(FP4_E_INVAL, "need 1 <= nquart <= 2^20");
+    if (!atoms || !cells || !phi) return ctx->fail(FP4_E_INVAL, "null pointer argument");
+    for (int i = 0; i < 4 * nquart; ++i)
+      if (atoms[i] < 0 || atoms[i] >= ctx->nat) return ctx->fail(FP4_E_INVAL, "quartet atom index out of range");
+    for (int i = 0; i < 9 * nquart; ++i)
+      if (cells[i] < -64 || cells[i] > 64) return ctx->fail(FP4_E_INVAL, "quartet cell coordinate outside [-64, 64]");
+    if (!finite_all(phi, (size_t)81 * nquart)) return ctx->fail(FP4_E_INVAL, "force constants contain NaN or Inf");
+    const int nat = ctx->nat;
+    // distinct cell vectors a = Rj - Rl, b = -Rl, d = Rk - Rl
+    using V3 = std::array<int, 3>;
+    std::map<V3, int> amap, bmap, dmap;
+    struct Q {
+      int i, j, k, l, a, b, d, n;
+    };
+    std::vector<Q> qs(nquart);
+    for (int n = 0; n < nquart; ++n) {
+      const int32_t *at = atoms + 4 * n, *cl = cells + 9 * n;
+      V3 Rj{cl[0], cl[1], cl[2]}, Rk{cl[3], cl[4], cl[5]}, Rl{cl[6], cl[7], cl[8]};
+      V3 a{Rj[0] - Rl[0], Rj[1] - Rl[1], Rj[2] - Rl[2]};
+      V3 b{-Rl[0], -Rl[1], -Rl[2]};
+      V3 d{Rk[0] - Rl[0], Rk[1] - Rl[1], Rk[2] - Rl[2]};
+      auto intern = [](std::map<V3, int> &m, const V3 &v) {
+        auto it = m.find(v);
+        if (it != m.end()) return it->second;
+        const int id = (int)m.size();
+        m.emplace(v, id);
+        return id;
+      };
+      qs[n] = Q{at[0], at[1], at[2], at[3], intern(amap, a), intern(bmap, b), intern(dmap, d), n};
+    }
+    // groups (k, l, d) and combos (group, j, a), ordered
+    std::sort(qs.begin(), qs.end(), [](const Q &x, const Q &y) {
+      return std::tie(x.k, x.l, x.d, x.j, x.a, x.n) < std::tie(y.k, y.l, y.d, y.j, y.a, y.n);
+    });
+    ctx->g_d.clear();
+    ctx->c_start.clear();
+    ctx->c_jat.clear();
+    ctx->c_a.clear();
+    ctx->cq_start.clear();
+    ctx->q_i.assign(nquart, 0);
+    ctx->q_b.assign(nquart, 0);
+    ctx->q_phi.assign((size_t)81 * nquart, 0.0);
+    ctx->kl_start.assign(nat * nat + 1, 0);
+    std::vector<int> g_kl;
+    for (int p = 0; p < nquart; ++p) {
+      const Q &q = qs[p];
+      const bool new_group = p == 0 || q.k != qs[p - 1].k || q.l != qs[p - 1].l || q.d != qs[p - 1].d;
+      if (new_group) {
+        ctx->g_d.push_back(q.d);
+        g_kl.push_back(q.k * nat + q.l);
+        ctx->c_start.push_back((int)ctx->c_jat.size());
+      }
+      const bool new_combo = new_group || q.j != qs[p - 1].j || q.a != qs[p - 1].a;
+      if (new_combo) {
+        ctx->c_jat.push_back(q.j);
+        ctx->c_a.push_back(q.a);
+        ctx->cq_start.push_back(p);
+      }
+      ctx->q_i[p] = q.i;
+      ctx->q_b[p] = q.b;
+      std::memcpy(&ctx->q_phi[(size_t)81 * p], phi + (size_t)81 * q.n, 81 * sizeof(double));
+    }
+    ctx->ng = (int)ctx->g_d.size();
+    ctx->nc = (int)ctx->c_jat.size();
+    ctx->nq4 = nquart;
+    ctx->c_start.push_back(ctx->nc);
+    ctx->cq_start.push_back(nquart);
+    // kl_start[kl] = first group with pair index >= kl
+    for (int kl = 0, g = 0; kl <= nat * nat; ++kl) {
+      while (g < ctx->ng && g_kl[g] < kl) ++g;
+      ctx->kl_start[kl] = g;
+    }
+    auto flat = [](const std::map<V3, int> &m) {
+      std::vector<int> v(3 * m.size());
+      for (auto &kv : m)
+        for (int x = 0; x < 3; ++x) v[3 * kv.second + x] = kv.first[x];
+      return v;
+    };
+    ctx->avec = flat(amap);
+    ctx->bvec = flat(bmap);
+    ctx->dvec = flat(dmap);
+    ctx->na = (int)amap.size();
+    ctx->nbv = (int)bmap.size();
+    ctx->nd = (int)dmap.size();
+    (void)hipSetDevice(ctx->device);
+    int rc;
+    if ((rc = upload(ctx, ctx->d_g_d, ctx->g_d.data(), ctx->g_d.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_kl, ctx->kl_start.data(), ctx->kl_start.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_cs, ctx->c_start.data(), ctx->c_start.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_cj, ctx->c_jat.data(), ctx->c_jat.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_ca, ctx->c_a.data(), ctx->c_a.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_cq, ctx->cq_start.data(), ctx->cq_start.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_qi, ctx->q_i.data(), ctx->q_i.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_qb, ctx->q_b.data(), ctx->q_b.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_qphi, ctx->q_phi.data(), ctx->q_phi.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_avec, ctx->avec.data(), ctx->avec.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_bvec, ctx->bvec.data(), ctx->bvec.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_dvec, ctx->dvec.data(), ctx->dvec.size()))) return rc;
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->have_fc4 = true;
+    ctx->tables_dirty = true;
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_set_param(fp4_ctx *ctx, int32_t key, double value) {
+  if (!ctx) return FP4_E_INVAL;
+  if (!std::isfinite(value)) return ctx->fail(FP4_E_INVAL, "parameter value must be finite");
+  switch (key) {
+    case FP4_PARAM_WINDOW_W:
+      if (!(value > 0.0)) return ctx->fail(FP4_E_INVAL, "window width must be > 0");
+      ctx->window_w = value;
+      return FP4_OK;
+    case FP4_PARAM_SIGMA_MIN:
+      if (!(value >= 0.0)) return ctx->fail(FP4_E_INVAL, "sigma_min must be >= 0");
+      ctx->sigma_min = value;
+      return FP4_OK;
+    case FP4_PARAM_QCHUNK:
+      if (!(value >= 0.0) || value > (1 << 20)) return ctx->fail(FP4_E_INVAL, "q' chunk must be in [0, 2^20]");
+      ctx->qchunk = (int)value;
+      return FP4_OK;
+    case FP4_PARAM_PROFILE:
+      ctx->profile = value != 0.0;
+      return FP4_OK;
+    default:
+      return ctx->fail(FP4_E_INVAL, "unknown parameter key");
+  }
+}
+
+int fp4_compute_rates4(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                       uint32_t mask, int32_t precision, double *rates,
+                       double *rates_by_channel, int64_t *counts) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    (void)hipSetDevice(ctx->device);
+    return compute_common(ctx, T, nT, scalebroad, mask, precision, nullptr, 0, rates,
+                          rates_by_channel, counts);
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_compute_rates4_subset(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                              uint32_t mask, int32_t precision, const int32_t *targets,
+                              int32_t ntargets, double *rates, double *rates_by_channel,
+                              int64_t *counts) {
+  if (!ctx) return FP4_E_INVAL;
+  if (!targets) return ctx->fail(FP4_E_INVAL, "targets must not be NULL");
+  try {
+    (void)hipSetDevice(ctx->device);
+    return compute_common(ctx, T, nT, scalebroad, mask, precision, targets, ntargets, rates,
+                          rates_by_channel, counts);
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_compute_rates4_async(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                             uint32_t mask, int32_t precision, void *hip_stream,
+                             double *d_rates, double *d_rates_by_channel, int64_t *d_counts) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    int rc = check_compute_args(ctx, T, nT, scalebroad, mask, precision);
+    if (rc) return rc;
+    if (!d_rates) return ctx->fail(FP4_E_INVAL, "d_rates is required");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nt = ctx->N * ctx->nb;
+    std::vector<int> tl(nt);
+    for (int i = 0; i < nt; ++i) tl[i] = i;
+    // the target list and temperatures are staged through the context's stream first
+    if ((rc = upload(ctx, ctx->d_targets, tl.data(), tl.size()))) return rc;
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const hipStream_t keep = ctx->stream;
+    ctx->stream = s;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t evi = 0;
+    rc = enqueue(ctx, T, nT, scalebroad, mask, precision, nt, s, d_rates, d_rates_by_channel,
+                 (long long *)d_counts, ctx->profile ? &ev : nullptr, &evi);
+    ctx->stream = keep;
+    if (rc) return rc;
+    if (ctx->profile) {
+      FP4_HIP(ctx, hipStreamSynchronize(s));
+      if ((rc = finish_stats(ctx, ev, nullptr, nullptr))) return rc;
+    }
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_debug_matrix_elements(fp4_ctx *ctx, int32_t n, const int32_t *quads, int32_t precision,
+                              double *V) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (!ctx->have_lattice || !ctx->have_modes || !ctx->have_fc4)
+      return ctx->fail(FP4_E_STATE, "debug call before all loads");
+    if (n < 1 || n > (1 << 16) || !quads || !V) return ctx->fail(FP4_E_INVAL, "need 1 <= n <= 2^16 and non-null buffers");
+    if (precision != FP4_FP64 && precision != FP4_FP32) return ctx->fail(FP4_E_UNSUPPORTED, "bad precision");
+    for (int p = 0; p < n; ++p) {
+      const int32_t *q = quads + 8 * p;
+      for (int s : {0, 2, 4})
+        if (q[s] < 0 || q[s] >= ctx->N) return ctx->fail(FP4_E_INVAL, "q index out of range");
+      for (int s : {1, 3, 5, 6})
+        if (q[s] < 0 || q[s] >= ctx->nb) return ctx->fail(FP4_E_INVAL, "branch index out of range");
+      if (q[7] < 0 || q[7] > 2) return ctx->fail(FP4_E_INVAL, "channel must be 0, 1 or 2");
+    }
+    (void)hipSetDevice(ctx->device);
+    int rc;
+    if ((rc = ensure_tables(ctx))) return rc;
+    // distinct targets -> slots of the precontraction buffer
+    std::map<int, int> slot;
+    std::vector<int> tl, ts(n);
+    for (int p = 0; p < n; ++p) {
+      const int mu = quads[8 * p] * ctx->nb + quads[8 * p + 1];
+      auto it = slot.find(mu);
+      if (it == slot.end()) {
+        it = slot.emplace(mu, (int)tl.size()).first;
+        tl.push_back(mu);
+      }
+      ts[p] = it->second;
+    }
+    const int fp32 = precision == FP4_FP32;
+    const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+    if ((rc = upload(ctx, ctx->d_targets, tl.data(), tl.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_quads, quads, (size_t)8 * n))) return rc;
+    if ((rc = upload(ctx, ctx->d_tslot, ts.data(), ts.size()))) return rc;
+    if ((rc = ensure(ctx, ctx->d_U, tl.size() * ctx->nc * 27 * cb))) return rc;
+    if ((rc = ensure(ctx, ctx->d_V, (size_t)n * sizeof(double2)))) return rc;
+    fp4::Crystal c = make_crystal(ctx);
+    FP4_HIP(ctx, fp4::launch_precontract(c, (const int *)ctx->d_targets.p, (int)tl.size(), fp32, ctx->d_U.p, ctx->stream));
+    FP4_HIP(ctx, fp4::launch_debug_v(c, (const int *)ctx->d_quads.p, n, (const int *)ctx->d_tslot.p, ctx->d_U.p, fp32, (double2 *)ctx->d_V.p, ctx->stream));
+    FP4_HIP(ctx, hipMemcpyAsync(V, ctx->d_V.p, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_last_stats(const fp4_ctx *ctx, int64_t *processes, int64_t *candidates, int64_t *blocks) {
+  if (!ctx) return FP4_E_INVAL;
+  if (processes) *processes = ctx->st_processes;
+  if (candidates) *candidates = ctx->st_candidates;
+  if (blocks) *blocks = ctx->st_blocks;
+  return FP4_OK;
+}
+
+int fp4_last_timing(const fp4_ctx *ctx, double *ms_main, double *ms_total) {
+  if (!ctx) return FP4_E_INVAL;
+  if (ms_main) *ms_main = ctx->ms_main;
+  if (ms_total) *ms_total = ctx->ms_total;
+  return FP4_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// fp4_internal.h -- structures shared by the host side and the HIP kernels of the
+// four-phonon rate library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fp4 {
+
+// Device-resident description of one crystal: grid, modes and the regrouped quartet list.
+//
+// Quartet regrouping.  For quartet n with atoms (i, j, k, l) and cells (0, Rj, Rk, Rl) the
+// phase of Eq. V4 for a momentum-conserving process is
+//   exp(i(s' q'.Rj + s'' q''.Rk - q'''.Rl)) = exp(i q.b) exp(i s' q'.a) exp(i s'' q''.d)
+// with b = -Rl, a = Rj - Rl, d = Rk - Rl.  Quartets are grouped by g = (k, l, d) ("groups")
+// and inside a group by (j, a) ("combos").  Groups are ordered by (k, l, d) so that the
+// groups of one (k, l) atom pair are contiguous.
+struct Crystal {
+  int g0, g1, g2, N;        // grid and number of q points
+  int nat, nb;              // atoms, branches (3 nat)
+  int ng, nc, nq4;          // groups, combos, quartets
+  int na, nbv, nd;          // distinct a, b, d cell vectors
+  const double *omega;      // [N*nb]
+  const double *inv_omega;  // [N*nb] 1/omega (0 for inactive modes)
+  const double4 *vel;       // [N*nb] (x, y, z, 0)
+  const double2 *E64;       // [N][nb][nb]  e_{j}(atom, x) / sqrt(M_atom), column = 3 atom + x
+  const float2 *E32;        // same, FP32
+  const int4 *qn;           // [N] (n1, n2, n3, 0)
+  const double2 *PHA64;     // [N][na]  exp(i q.a)
+  const double2 *PHB64;     // [N][nbv] exp(i q.b)
+  const double2 *PHD64;     // [N][nd]  exp(i q.d)
+  const float2 *PHD32;      // [N][nd]
+  const int *g_d;           // [ng] index of d
+  const int *kl_start;      // [nat*nat + 1] first group of atom pair (k, l)
+  const int *c_start;       // [ng + 1] first combo of group g
+  const int *c_jat;         // [nc] slot-2 atom j of combo c
+  const int *c_a;           // [nc] index of a
+  const int *cq_start;      // [nc + 1] first quartet (combo order) of combo c
+  const int *q_i;           // [nq4] slot-1 atom i (combo order)
+  const int *q_b;           // [nq4] index of b (combo order)
+  const double *q_phi;      // [nq4][81] (combo order)
+};
+
+// Per-call parameters of the rate kernel.
+struct RateArgs {
+  double c_win;             // ((W sb) dq)^2 : keep <=> dw^2 <= c_win s2
+  double c_sig;             // (sb dq)^2     : sigma^2 = c_sig s2
+  double c_min;             // sigma_min^2   : delta := 1 below
+  double kpref;             // C4 / N^2
+  int nT;
+  uint32_t mask;            // channel bits
+  const double *occ;        // [nT][N*nb]  n0 (0 for inactive modes)
+  const double *inv_occ;    // [nT][N*nb]  1/n0 = expm1(hbar w / kT)
+  const int *targets;       // [nt] mode ids
+  int nt;                   // targets in this batch
+  int t0;                   // index of the first target of the batch in the output
+  int qchunk;               // q' points per work-group
+  int nchunk;               // ceil(N / qchunk)
+  const void *U;            // [nt][nc][27] complex (R) precontraction of the batch
+  double *partial;          // [nt_total][nchunk][3][nT]
+  unsigned long long *pcount; // [nt_total][nchunk][3]
+  unsigned long long *blocks; // [1] contracted branch blocks (atomic)
+};
+
+// launchers (fp4_kernels.hip)
+hipError_t launch_tables(const Crystal &c, double *inv_omega, double2 *E64, float2 *E32,
+                         const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
+                         double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
+                         const int *dvec, hipStream_t s);
+hipError_t launch_occupations(const Crystal &c, const double *T, int nT, double hbar_over_kb,
+                              double *occ, double *inv_occ, hipStream_t s);
+hipError_t launch_precontract(const Crystal &c, const int *targets, int nt, int fp32,
+                              void *U, hipStream_t s);
+hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream_t s);
+hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double *rates_ch,
+                         long long *counts, hipStream_t s);
+hipError_t launch_debug_v(const Crystal &c, const int *quads, int n, const int *tslot,
+                          const void *U, int fp32, double2 *V, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace fp4

@@ -1,0 +1,667 @@
+// fp4_kernels.hip -- CDNA4 (gfx950) kernels of the four-phonon RTA rate.
+//
+// Hot path (FourPhonon paper, Eq. tao0, Eq. 4phgamma, Eq. V4, Sec. 2.4):
+//   k_tables       per-q tables: E = e/sqrt(M), grid triples, lattice phase tables
+//   k_occupations  n0 and 1/n0 for every mode and temperature
+//   k_precontract  per target mode lambda: U_c = sum over the quartets of combo c of
+//                  Phi contracted with the slot-1 factor e^lambda(i) exp(i q.b)
+//   k_rates        per (lambda, block of q'): W'' for each lambda' (slot-2 contraction,
+//                  grouped by slot-3/slot-4 atoms and relative cell), then for every q'' and
+//                  channel: FP64 energy-window prefilter of the nb x nb branch block, and for
+//                  blocks with a surviving process the branch-block contraction
+//                  V = E3 F E4^T with F = sum_d exp(i s'' q''.d) W''_d, followed by the
+//                  Gaussian, occupation factors and per-lane FP64 accumulation
+//   k_reduce       ordered sum of the per-work-group partial rates
+#include "fp4_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace fp4 {
+namespace {
+
+// ------------------------------------------------------------------ complex helpers
+
+template <typename R> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename V> __device__ __forceinline__ V czero() { V z; z.x = 0; z.y = 0; return z; }
+template <typename V> __device__ __forceinline__ V cconj(V a) { a.y = -a.y; return a; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = fmaR(a.x, b.x, -a.y * b.y);
+  r.y = fmaR(a.x, b.y, a.y * b.x);
+  return r;
+}
+// acc += a * b
+template <typename V> __device__ __forceinline__ void cmac(V &acc, V a, V b) {
+  acc.x = fmaR(a.x, b.x, acc.x);
+  acc.x = fmaR(-a.y, b.y, acc.x);
+  acc.y = fmaR(a.x, b.y, acc.y);
+  acc.y = fmaR(a.y, b.x, acc.y);
+}
+// acc += a * conj(b)
+template <typename V> __device__ __forceinline__ void cmac_cb(V &acc, V a, V b) {
+  acc.x = fmaR(a.x, b.x, acc.x);
+  acc.x = fmaR(a.y, b.y, acc.x);
+  acc.y = fmaR(-a.x, b.y, acc.y);
+  acc.y = fmaR(a.y, b.x, acc.y);
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { a.x += b.x; a.y += b.y; return a; }
+
+__device__ __forceinline__ float2 to32(double2 a) { return make_float2((float)a.x, (float)a.y); }
+template <typename V> __device__ __forceinline__ V fromd(double2 a);
+template <> __device__ __forceinline__ double2 fromd<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 fromd<float2>(double2 a) { return to32(a); }
+
+template <typename R> __device__ __forceinline__ const typename CT<R>::T *Etab(const Crystal &c);
+template <> __device__ __forceinline__ const double2 *Etab<double>(const Crystal &c) { return c.E64; }
+template <> __device__ __forceinline__ const float2 *Etab<float>(const Crystal &c) { return c.E32; }
+template <typename R> __device__ __forceinline__ const typename CT<R>::T *PHDtab(const Crystal &c);
+template <> __device__ __forceinline__ const double2 *PHDtab<double>(const Crystal &c) { return c.PHD64; }
+template <> __device__ __forceinline__ const float2 *PHDtab<float>(const Crystal &c) { return c.PHD32; }
+
+// exp(2 pi i k / N) with exact conjugate symmetry between k and N - k
+__device__ __forceinline__ double2 root_of_unity(long long k, int N) {
+  const bool upper = 2 * k > N;
+  const long long kk = upper ? N - k : k;
+  double s, co;
+  sincospi(2.0 * (double)kk / (double)N, &s, &co);
+  return make_double2(co, upper ? -s : s);
+}
+
+__device__ __forceinline__ int wrap(int x, int g) {
+  x = x >= g ? x - g : x;
+  x = x >= g ? x - g : x;
+  x = x < 0 ? x + g : x;
+  x = x < 0 ? x + g : x;
+  return x;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Energy-window predicate in a fixed FP64 order without contraction:
+//   dw = bw - w3 (bw = (w s' w') s'' w'' formed by the caller, left to right)
+//   s2 = (dx*dx + dy*dy) + dz*dz, d = v'' - v'''
+//   keep <=> dw*dw <= c_win * s2
+__device__ __forceinline__ bool window_keep(double bw, double w3, double4 v2, double4 v3,
+                                            double c_win, double &dw, double &s2) {
+#pragma clang fp contract(off)
+  dw = bw - w3;
+  const double dx = v2.x - v3.x, dy = v2.y - v3.y, dz = v2.z - v3.z;
+  s2 = (dx * dx + dy * dy) + dz * dz;
+  return dw * dw <= c_win * s2;
+}
+
+__device__ __forceinline__ double add_signed(double a, double b, int s) {
+#pragma clang fp contract(off)
+  return s > 0 ? a + b : a - b;
+}
+
+// ------------------------------------------------------------------ table kernels
+
+__global__ void k_tables(Crystal c, double *inv_omega, double2 *E64, float2 *E32,
+                         const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
+                         double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
+                         const int *dvec) {
+  const int iq = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iq >= c.N) return;
+  const int n1 = iq % c.g0, n2 = (iq / c.g0) % c.g1, n3 = iq / (c.g0 * c.g1);
+  qn[iq] = make_int4(n1, n2, n3, 0);
+  const int nb = c.nb;
+  for (int j = 0; j < nb; ++j) {
+    const double w = c.omega[(size_t)iq * nb + j];
+    inv_omega[(size_t)iq * nb + j] = w > 0.0 ? 1.0 / w : 0.0;
+  }
+  for (int j = 0; j < nb; ++j)
+    for (int col = 0; col < nb; ++col) {
+      const size_t o = ((size_t)iq * nb + j) * nb + col;
+      const double sm = 1.0 / sqrt(mass[col / 3]);
+      const double2 e = make_double2(evec[2 * o] * sm, evec[2 * o + 1] * sm);
+      E64[o] = e;
+      E32[o] = to32(e);
+    }
+  auto phase = [&](const int *R) {
+    const long long k = (long long)(((long long)n1 * R[0]) % c.g0 + c.g0) % c.g0 * (c.N / c.g0) +
+                        (long long)(((long long)n2 * R[1]) % c.g1 + c.g1) % c.g1 * (c.N / c.g1) +
+                        (long long)(((long long)n3 * R[2]) % c.g2 + c.g2) % c.g2 * (c.N / c.g2);
+    return root_of_unity(k % c.N, c.N);
+  };
+  for (int i = 0; i < c.na; ++i) PHA64[(size_t)iq * c.na + i] = phase(avec + 3 * i);
+  for (int i = 0; i < c.nbv; ++i) PHB64[(size_t)iq * c.nbv + i] = phase(bvec + 3 * i);
+  for (int i = 0; i < c.nd; ++i) {
+    const double2 p = phase(dvec + 3 * i);
+    PHD64[(size_t)iq * c.nd + i] = p;
+    PHD32[(size_t)iq * c.nd + i] = to32(p);
+  }
+}
+
+// n0 = 1/expm1(hbar w / k T) (after Eq. 4phgamma); 1/n0 = expm1(.)  (0 for inactive modes)
+__global__ void k_occupations(const double *omega, int nmodes, const double *T, int nT,
+                              double hk, double *occ, double *inv_occ) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nmodes * nT) return;
+  const int t = i / nmodes, m = i % nmodes;
+  const double w = omega[m];
+  if (w > 0.0) {
+    const double em = expm1(hk * w / T[t]);
+    occ[i] = 1.0 / em;
+    inv_occ[i] = em;
+  } else {
+    occ[i] = 0.0;
+    inv_occ[i] = 0.0;
+  }
+}
+
+// U[t][c][beta*9 + gamma*3 + theta] = sum_{n in combo c} sum_alpha Phi_n^{abgt}
+//                                     e^{lambda_t}_alpha(i_n)/sqrt(M) exp(i q.b_n)
+template <typename CR>
+__global__ void k_precontract(Crystal c, const int *targets, int nt, CR *U) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)nt * c.nc * 27;
+  if (id >= total) return;
+  const int e = (int)(id % 27);
+  const long long tc = id / 27;
+  const int ci = (int)(tc % c.nc);
+  const int t = (int)(tc / c.nc);
+  const int mu = targets[t];
+  const int iq = mu / c.nb, j = mu % c.nb;
+  const double2 *e1 = c.E64 + ((size_t)iq * c.nb + j) * c.nb;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int n = c.cq_start[ci]; n < c.cq_start[ci + 1]; ++n) {
+    const int i = c.q_i[n];
+    const double2 ph = c.PHB64[(size_t)iq * c.nbv + c.q_b[n]];
+    const double *phi = c.q_phi + 81 * (size_t)n + e;
+    for (int al = 0; al < 3; ++al) {
+      const double2 x = cmul(e1[3 * i + al], ph);
+      const double f = phi[27 * al];
+      acc.x = fma(f, x.x, acc.x);
+      acc.y = fma(f, x.y, acc.y);
+    }
+  }
+  U[id] = fromd<CR>(acc);
+}
+
+// ------------------------------------------------------------------ W'' build
+
+// W[s][g][gamma*3 + theta], s = 0 for s' = + and 1 for s' = -:
+//   sum over combos c of g, beta: U_c[beta][gt] (E[q'][j'][3 j_c + beta] exp(i q'.a_c))^(s')
+template <typename R>
+__device__ void build_W(const Crystal &c, const typename CT<R>::T *Ut, int iq1, int j1,
+                        typename CT<R>::T *W, int tid, int nthr) {
+  using CR = typename CT<R>::T;
+  const CR *e2 = Etab<R>(c) + ((size_t)iq1 * c.nb + j1) * c.nb;
+  const int tot = c.ng * 9;
+  for (int idx = tid; idx < tot; idx += nthr) {
+    const int g = idx / 9, gt = idx - 9 * g;
+    CR ap = czero<CR>(), am = czero<CR>();
+    for (int ci = c.c_start[g]; ci < c.c_start[g + 1]; ++ci) {
+      const int jat = c.c_jat[ci];
+      const CR ph = fromd<CR>(c.PHA64[(size_t)iq1 * c.na + c.c_a[ci]]);
+      const CR *u = Ut + (size_t)ci * 27 + gt;
+#pragma unroll
+      for (int be = 0; be < 3; ++be) {
+        const CR p = cmul(e2[3 * jat + be], ph);
+        const CR uu = u[9 * be];
+        cmac(ap, uu, p);
+        cmac_cb(am, uu, p);
+      }
+    }
+    W[idx] = ap;
+    W[tot + idx] = am;
+  }
+}
+
+// ------------------------------------------------------------------ branch block
+
+// Row r (= j'') of V[j''][j'''] for the block (lambda, lambda', q'', channel with sign S2):
+//   F[(k,gamma)][(l,theta)] = sum_{d of (k,l)} exp(i s'' q''.d) W[(k,l,d)][gamma theta]
+//   V = E3 F E4^T,  E3[j''][(k,gamma)] = (E[q''][j''][3k+gamma])^(s''),
+//                   E4[j'''][(l,theta)] = conj(E[q'''][j'''][3l+theta])
+// The nb lanes of a group hold one row each and exchange F rows and E4 rows through the
+// group's LDS tile Xg[nb][nb] (all lanes of a group belong to one wavefront).
+template <typename R, int NB, int S2>
+__device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>::T *Ws,
+                                          int iq2, int iq3, int r,
+                                          typename CT<R>::T *Xg, typename CT<R>::T (&V)[NB]) {
+  using CR = typename CT<R>::T;
+  constexpr int NAT = NB / 3;
+  const int k = r / 3, gam = r - 3 * k;
+  const CR *phd = PHDtab<R>(c) + (size_t)iq2 * c.nd;
+  // F row r, accumulated in the atom order l = k, k+1, ... (mod NAT) so that the
+  // register index is static
+  CR Frel[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) Frel[i] = czero<CR>();
+#pragma unroll
+  for (int rl = 0; rl < NAT; ++rl) {
+    const int l = (k + rl) % NAT;
+    const int gb = c.kl_start[k * NAT + l], ge = c.kl_start[k * NAT + l + 1];
+    for (int g = gb; g < ge; ++g) {
+      CR ph = phd[c.g_d[g]];
+      if (S2 < 0) ph = cconj(ph);
+      const CR *wg = Ws + g * 9 + gam * 3;
+#pragma unroll
+      for (int th = 0; th < 3; ++th) cmac(Frel[rl * 3 + th], ph, wg[th]);
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < NAT; ++l) {
+    const int rl = (l - k + NAT) % NAT;
+#pragma unroll
+    for (int th = 0; th < 3; ++th) {
+      CR f = Frel[th];
+#pragma unroll
+      for (int rr = 1; rr < NAT; ++rr)
+        if (rr == rl) f = Frel[rr * 3 + th];
+      Xg[r * NB + l * 3 + th] = f;
+    }
+  }
+  wave_sync();
+  // H = E3[r][:] F
+  const CR *e3 = Etab<R>(c) + ((size_t)iq2 * NB + r) * NB;
+  CR H[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) H[i] = czero<CR>();
+#pragma unroll
+  for (int kg = 0; kg < NB; ++kg) {
+    CR e = e3[kg];
+    if (S2 < 0) e = cconj(e);
+#pragma unroll
+    for (int col = 0; col < NB; ++col) cmac(H[col], e, Xg[kg * NB + col]);
+    __asm__ volatile("" ::: "memory");   // bound the number of tile rows in flight
+  }
+  wave_sync();
+  // E4 rows: lane r writes row r = conj(E[q'''][r][:])
+  const CR *e4 = Etab<R>(c) + ((size_t)iq3 * NB + r) * NB;
+#pragma unroll
+  for (int col = 0; col < NB; ++col) Xg[r * NB + col] = cconj(e4[col]);
+  wave_sync();
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    CR v = czero<CR>();
+#pragma unroll
+    for (int col = 0; col < NB; ++col) cmac(v, H[col], Xg[cc * NB + col]);
+    V[cc] = v;
+    __asm__ volatile("" ::: "memory");
+  }
+  wave_sync();
+}
+
+// ------------------------------------------------------------------ rate kernel
+
+template <int NT>
+struct Acc {
+  double r[3][NT];
+  unsigned cnt[3];
+  unsigned blocks;
+};
+
+// All blocks (q'') of one channel for fixed lambda, lambda'.  Group G of the work-group
+// handles q'' = G, G + NGRP, ...; lane r of the group owns branch row j'' = r.
+template <typename R, int NB, int NT, int CH>
+__device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs &a,
+                                               const typename CT<R>::T *W, int G, int NGRP,
+                                               int gw, int r, typename CT<R>::T *Xg,
+                                               int4 nq, int4 nq1, int mu, int mu1, double w,
+                                               double w1, const double (&invn)[NT],
+                                               const double (&n1)[NT], Acc<NT> &acc) {
+  using CR = typename CT<R>::T;
+  constexpr int S1 = (CH == 2) ? -1 : 1;
+  constexpr int S2 = (CH == 0) ? 1 : -1;
+  constexpr double WCH = (CH == 2) ? (1.0 / 6.0) : 0.5;
+  const CR *Ws = W + (S1 > 0 ? 0 : c.ng * 9);
+  const double aw = add_signed(w, w1, S1);
+  // weight of the channel (Eq. tao0), prefactor C4/N^2 and 1/(w w') of Eq. 4phgamma
+  const double kw = WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
+  for (int iq2 = G; iq2 < c.N; iq2 += NGRP) {
+    const int4 nq2 = c.qn[iq2];
+    const int x = wrap(nq.x + S1 * nq1.x + S2 * nq2.x, c.g0);
+    const int y = wrap(nq.y + S1 * nq1.y + S2 * nq2.y, c.g1);
+    const int z = wrap(nq.z + S1 * nq1.z + S2 * nq2.z, c.g2);
+    const int iq3 = x + c.g0 * (y + c.g1 * z);
+    // FP64 window prefilter of this lane's row (j'' = r) against every j'''
+    const int mu2 = iq2 * NB + r;
+    const double w2 = c.omega[mu2];
+    const double4 v2 = c.vel[mu2];
+    const double bw = add_signed(aw, w2, S2);
+    unsigned bits = 0;
+    if (w2 > 0.0) {
+#pragma unroll 2
+      for (int cc = 0; cc < NB; ++cc) {
+        const int mu3 = iq3 * NB + cc;
+        const double w3 = c.omega[mu3];
+        double dw, s2;
+        if (w3 > 0.0 && window_keep(bw, w3, v2, c.vel[mu3], a.c_win, dw, s2)) bits |= 1u << cc;
+      }
+    }
+    const unsigned long long bal = __ballot(bits != 0u);
+    const unsigned long long gbits = (bal >> (gw * NB)) & ((1ull << NB) - 1ull);
+    if (gbits == 0ull) continue;           // no surviving process in this branch block
+    if (r == 0) acc.blocks += 1;
+    CR V[NB];
+    block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, V);
+    if (bits == 0u) continue;
+    // the lane's row of V goes through its own row of the group tile, so that the
+    // survivor loop below is not unrolled
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
+    const double kw2 = kw * c.inv_omega[mu2];
+    double n2[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) n2[t] = (t < a.nT) ? a.occ[(size_t)t * c.N * NB + mu2] : 0.0;
+#pragma unroll 1
+    for (int cc = 0; cc < NB; ++cc) {
+      if (!((bits >> cc) & 1u)) continue;
+      const int mu3 = iq3 * NB + cc;
+      const double w3 = c.omega[mu3];
+      double dw, s2;
+      window_keep(bw, w3, v2, c.vel[mu3], a.c_win, dw, s2);
+      const CR vv = Xg[r * NB + cc];
+      const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
+      const double sig2 = a.c_sig * s2;
+      double delta = 1.0;
+      if (!(sig2 < a.c_min)) {
+        // adaptive Gaussian, 1/sqrt(pi) = 0.5641895835477563
+        const double is2 = 1.0 / sig2;
+        delta = exp(-(dw * dw) * is2) * (0.5641895835477563 * sqrt(is2));
+      }
+      const double base = kw2 * c.inv_omega[mu3] * v2abs * delta;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t < a.nT) {
+          const double n3 = a.occ[(size_t)t * c.N * NB + mu3];
+          double f;
+          if (CH == 0) f = (1.0 + n1[t]) * (1.0 + n2[t]) * n3;
+          else if (CH == 1) f = (1.0 + n1[t]) * n2[t] * n3;
+          else f = n1[t] * n2[t] * n3;
+          acc.r[CH][t] += base * f * invn[t];
+        }
+      }
+      acc.cnt[CH] += 1;
+    }
+  }
+}
+
+template <typename R, int NB, int NT>
+__global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
+  using CR = typename CT<R>::T;
+  constexpr int GPW = 64 / NB;
+  constexpr int NGRP = 4 * GPW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  CR *W = reinterpret_cast<CR *>(smem);                 // [2][ng][9]
+  CR *X = W + 2 * c.ng * 9;                             // [NGRP][NB][NB]
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int gw = lane / NB, r = lane - gw * NB;
+  const bool glane = gw < GPW;
+  const int G = wave * GPW + gw;
+  CR *Xg = X + (size_t)(glane ? G : 0) * NB * NB;
+
+  const int t = blockIdx.x / a.nchunk, chunk = blockIdx.x - t * a.nchunk;
+  const int mu = a.targets[t];
+  const int iq = mu / NB;
+  Acc<NT> acc;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc.r[ch][tt] = 0.0;
+    acc.cnt[ch] = 0;
+  }
+  acc.blocks = 0;
+  const double w = c.omega[mu];
+  if (w > 0.0) {
+    const int4 nq = c.qn[iq];
+    const CR *Ut = reinterpret_cast<const CR *>(a.U) + (size_t)t * c.nc * 27;
+    double invn[NT];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) invn[tt] = (tt < a.nT) ? a.inv_occ[(size_t)tt * c.N * NB + mu] : 0.0;
+    const int q1b = chunk * a.qchunk;
+    const int q1e = min(c.N, q1b + a.qchunk);
+    for (int iq1 = q1b; iq1 < q1e; ++iq1) {
+      const int4 nq1 = c.qn[iq1];
+      for (int j1 = 0; j1 < NB; ++j1) {
+        const int mu1 = iq1 * NB + j1;
+        const double w1 = c.omega[mu1];
+        if (!(w1 > 0.0)) continue;
+        __syncthreads();
+        build_W<R>(c, Ut, iq1, j1, W, tid, 256);
+        __syncthreads();
+        if (!glane) continue;
+        double n1[NT];
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) n1[tt] = (tt < a.nT) ? a.occ[(size_t)tt * c.N * NB + mu1] : 0.0;
+        if (a.mask & 1u)
+          channel_blocks<R, NB, NT, 0>(c, a, W, G, NGRP, gw, r, Xg, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+        if (a.mask & 2u)
+          channel_blocks<R, NB, NT, 1>(c, a, W, G, NGRP, gw, r, Xg, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+        if (a.mask & 4u)
+          channel_blocks<R, NB, NT, 2>(c, a, W, G, NGRP, gw, r, Xg, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+      }
+    }
+  }
+  // work-group reduction in a fixed order: wave shuffles, then the four waves in order
+  __syncthreads();
+  double *red = reinterpret_cast<double *>(smem);
+  constexpr int NV = 3 * NT;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      double v = acc.r[ch][tt];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) red[wave * NV + ch * NT + tt] = v;
+    }
+  unsigned long long cv[4] = {acc.cnt[0], acc.cnt[1], acc.cnt[2], acc.blocks};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    unsigned long long v = cv[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    cv[i] = v;
+  }
+  unsigned long long *redc = reinterpret_cast<unsigned long long *>(red + 4 * NV);
+  if (lane == 0)
+    for (int i = 0; i < 4; ++i) redc[wave * 4 + i] = cv[i];
+  __syncthreads();
+  const size_t pbase = ((size_t)(a.t0 + t) * a.nchunk + chunk);
+  if (tid < NV) {
+    const int ch = tid / NT, tt = tid - ch * NT;
+    if (tt < a.nT) {
+      const double v = ((red[tid] + red[NV + tid]) + red[2 * NV + tid]) + red[3 * NV + tid];
+      a.partial[pbase * 3 * a.nT + ch * a.nT + tt] = v;
+    }
+  }
+  if (tid < 3) a.pcount[pbase * 3 + tid] = redc[tid] + redc[4 + tid] + redc[8 + tid] + redc[12 + tid];
+  if (tid == 0) {
+    const unsigned long long b = redc[3] + redc[7] + redc[11] + redc[15];
+    if (b) atomicAdd(a.blocks, b);
+  }
+}
+
+// ordered reduction over q'-chunks: rates[T][t], per channel, counts
+__global__ void k_reduce(const double *partial, const unsigned long long *pcount, int nt,
+                         int nchunk, int nT, double *rates, double *rates_ch,
+                         long long *counts) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  for (int tt = 0; tt < nT; ++tt) {
+    double tot = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+      double s = 0.0;
+      for (int k = 0; k < nchunk; ++k) s += partial[(((size_t)t * nchunk + k) * 3 + ch) * nT + tt];
+      if (rates_ch) rates_ch[((size_t)tt * 3 + ch) * nt + t] = s;
+      tot += s;
+    }
+    rates[(size_t)tt * nt + t] = tot;
+  }
+  if (counts)
+    for (int ch = 0; ch < 3; ++ch) {
+      unsigned long long s = 0;
+      for (int k = 0; k < nchunk; ++k) s += pcount[((size_t)t * nchunk + k) * 3 + ch];
+      counts[(size_t)t * 3 + ch] = (long long)s;
+    }
+}
+
+// V for explicit processes through the same W'' build and branch-block contraction.
+// One wavefront per process; lanes 0..NB-1 form the group.
+template <typename R, int NB>
+__global__ __launch_bounds__(64) void k_debug_v(Crystal c, const int *quads, const int *tslot,
+                                                const typename CT<R>::T *U, double2 *Vout) {
+  using CR = typename CT<R>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  CR *W = reinterpret_cast<CR *>(smem);
+  CR *Xg = W + 2 * c.ng * 9;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int *qd = quads + 8 * p;
+  const int iq = qd[0], iq1 = qd[2], j1 = qd[3], iq2 = qd[4], j2 = qd[5], j3 = qd[6], ch = qd[7];
+  const CR *Ut = U + (size_t)tslot[p] * c.nc * 27;
+  build_W<R>(c, Ut, iq1, j1, W, tid, 64);
+  __syncthreads();
+  if (tid >= NB) return;
+  const int s1 = ch == 2 ? -1 : 1, s2 = ch == 0 ? 1 : -1;
+  const int4 nq = c.qn[iq], nq1 = c.qn[iq1], nq2 = c.qn[iq2];
+  const int x = wrap(nq.x + s1 * nq1.x + s2 * nq2.x, c.g0);
+  const int y = wrap(nq.y + s1 * nq1.y + s2 * nq2.y, c.g1);
+  const int z = wrap(nq.z + s1 * nq1.z + s2 * nq2.z, c.g2);
+  const int iq3 = x + c.g0 * (y + c.g1 * z);
+  CR V[NB];
+  const CR *Ws = W + (s1 > 0 ? 0 : c.ng * 9);
+  if (s2 > 0) block_row<R, NB, 1>(c, Ws, iq2, iq3, tid, Xg, V);
+  else block_row<R, NB, -1>(c, Ws, iq2, iq3, tid, Xg, V);
+  if (tid == j2) {
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc)
+      if (cc == j3) Vout[p] = make_double2((double)V[cc].x, (double)V[cc].y);
+  }
+}
+
+__global__ void k_zero(unsigned long long *p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+template <typename R, int NB, int NT>
+hipError_t launch_rates_t(const Crystal &c, const RateArgs &a, hipStream_t s) {
+  using CR = typename CT<R>::T;
+  constexpr int GPW = 64 / NB;
+  const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB);
+  const size_t lds_red = sizeof(double) * 4 * 3 * NT + sizeof(unsigned long long) * 16;
+  const size_t bytes = lds > lds_red ? lds : lds_red;
+  if (bytes > 160 * 1024) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)((size_t)a.nt * a.nchunk);
+  hipLaunchKernelGGL((k_rates<R, NB, NT>), dim3(grid), dim3(256), bytes, s, c, a);
+  return hipGetLastError();
+}
+
+template <typename R, int NB>
+hipError_t launch_rates_nb(const Crystal &c, const RateArgs &a, hipStream_t s) {
+  if (a.nT <= 1) return launch_rates_t<R, NB, 1>(c, a, s);
+  if (a.nT <= 2) return launch_rates_t<R, NB, 2>(c, a, s);
+  if (a.nT <= 4) return launch_rates_t<R, NB, 4>(c, a, s);
+  return launch_rates_t<R, NB, 8>(c, a, s);
+}
+
+template <typename R>
+hipError_t launch_rates_r(const Crystal &c, const RateArgs &a, hipStream_t s) {
+  switch (c.nb) {
+    case 3: return launch_rates_nb<R, 3>(c, a, s);
+    case 6: return launch_rates_nb<R, 6>(c, a, s);
+    case 9: return launch_rates_nb<R, 9>(c, a, s);
+    case 12: return launch_rates_nb<R, 12>(c, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, int NB>
+hipError_t launch_debug_nb(const Crystal &c, const int *quads, int n, const int *tslot,
+                           const void *U, double2 *V, hipStream_t s) {
+  using CR = typename CT<R>::T;
+  const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)NB * NB);
+  hipLaunchKernelGGL((k_debug_v<R, NB>), dim3(n), dim3(64), lds, s, c, quads, tslot,
+                     reinterpret_cast<const CR *>(U), V);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_debug_r(const Crystal &c, const int *quads, int n, const int *tslot,
+                          const void *U, double2 *V, hipStream_t s) {
+  switch (c.nb) {
+    case 3: return launch_debug_nb<R, 3>(c, quads, n, tslot, U, V, s);
+    case 6: return launch_debug_nb<R, 6>(c, quads, n, tslot, U, V, s);
+    case 9: return launch_debug_nb<R, 9>(c, quads, n, tslot, U, V, s);
+    case 12: return launch_debug_nb<R, 12>(c, quads, n, tslot, U, V, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tables(const Crystal &c, double *inv_omega, double2 *E64, float2 *E32,
+                         const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
+                         double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
+                         const int *dvec, hipStream_t s) {
+  const int nthr = 128;
+  hipLaunchKernelGGL(k_tables, dim3((c.N + nthr - 1) / nthr), dim3(nthr), 0, s, c, inv_omega, E64, E32,
+                     evec, mass, qn, PHA64, PHB64, PHD64, PHD32, avec, bvec, dvec);
+  return hipGetLastError();
+}
+
+hipError_t launch_occupations(const Crystal &c, const double *T, int nT, double hk,
+                              double *occ, double *inv_occ, hipStream_t s) {
+  const int n = c.N * c.nb * nT, nthr = 256;
+  hipLaunchKernelGGL(k_occupations, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, c.omega,
+                     c.N * c.nb, T, nT, hk, occ, inv_occ);
+  return hipGetLastError();
+}
+
+hipError_t launch_precontract(const Crystal &c, const int *targets, int nt, int fp32, void *U,
+                              hipStream_t s) {
+  const long long total = (long long)nt * c.nc * 27;
+  const int nthr = 256;
+  const unsigned grid = (unsigned)((total + nthr - 1) / nthr);
+  if (fp32)
+    hipLaunchKernelGGL(k_precontract<float2>, dim3(grid), dim3(nthr), 0, s, c, targets, nt,
+                       reinterpret_cast<float2 *>(U));
+  else
+    hipLaunchKernelGGL(k_precontract<double2>, dim3(grid), dim3(nthr), 0, s, c, targets, nt,
+                       reinterpret_cast<double2 *>(U));
+  return hipGetLastError();
+}
+
+hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream_t s) {
+  return fp32 ? launch_rates_r<float>(c, a, s) : launch_rates_r<double>(c, a, s);
+}
+
+hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double *rates_ch,
+                         long long *counts, hipStream_t s) {
+  const int nthr = 128;
+  hipLaunchKernelGGL(k_reduce, dim3((nt_total + nthr - 1) / nthr), dim3(nthr), 0, s,
+                     a.partial, a.pcount, nt_total, a.nchunk, a.nT, rates, rates_ch, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_v(const Crystal &c, const int *quads, int n, const int *tslot,
+                          const void *U, int fp32, double2 *V, hipStream_t s) {
+  return fp32 ? launch_debug_r<float>(c, quads, n, tslot, U, V, s)
+              : launch_debug_r<double>(c, quads, n, tslot, U, V, s);
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 8;
+  if (n == 0) return hipSuccess;
+  const int nthr = 256;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + nthr - 1) / nthr)), dim3(nthr), 0, s,
+                     reinterpret_cast<unsigned long long *>(p), n);
+  return hipGetLastError();
+}
+
+}  // namespace fp4

@@ -1,0 +1,238 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: kept-process counts bit-exact (the window predicate is FP64 in a fixed order on both
+sides); FP64 rates within 1e-10 relative; FP32-contraction rates within 1e-4 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.crystal import grid_points, flat_index, minus_index
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-10
+RTOL32 = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fp4():
+    import paper_2104_04895_amd as m
+    return m
+
+
+def _ctx(fp4, inst, **kw):
+    c = fp4.Context(0)
+    c.load_instance(inst, dq=oracle.default_dq(inst.cr.A, inst.grid), **kw)
+    return c
+
+
+def _oracle(inst, T, sb, mask, targets=None, want_rates=True, phi_scale=1.0):
+    m = oracle.Model.from_instance(inst, phi_scale=phi_scale)
+    return oracle.rates4(m, T, sb, mask, oracle.default_dq(inst.cr.A, inst.grid), targets,
+                         want_rates=want_rates)
+
+
+def _rel(a, b):
+    den = np.maximum(np.abs(b), 1e-300)
+    return np.max(np.where(b == 0, np.abs(a), np.abs(a - b) / den))
+
+
+@pytest.fixture(scope="module")
+def small():
+    return synth.small()
+
+
+def test_small_fp64_all_modes(fp4, small):
+    """3x3x3 diamond, first-shell FC4, 300 K, all 162 modes: counts exact, rates 1e-10."""
+    _say("case: small 3x3x3 fp64 all modes")
+    r_o, rch_o, c_o = _oracle(small, small.T, 1.0, 7)
+    with _ctx(fp4, small) as c:
+        r, rch, cnt = c.compute_rates4(small.T, 1.0, 7, fp4.FP4_FP64, by_channel=True)
+    assert np.array_equal(cnt, c_o)
+    assert _rel(r, r_o) <= RTOL64
+    assert _rel(rch, rch_o) <= RTOL64
+    assert np.all(r[0, :3] == 0.0)
+
+
+def test_small_fp32_contraction(fp4, small):
+    """Same workload with the complex-FP32 contraction: identical counts, rates 1e-4."""
+    _say("case: small 3x3x3 fp32")
+    r_o, _, c_o = _oracle(small, small.T, 1.0, 7)
+    with _ctx(fp4, small) as c:
+        r, _, cnt = c.compute_rates4(small.T, 1.0, 7, fp4.FP4_FP32)
+    assert np.array_equal(cnt, c_o)
+    err = _rel(r, r_o)
+    _say("fp32 max rel err", err)
+    assert err <= RTOL32
+
+
+@pytest.mark.parametrize("grid,rc,sb,mask,T", [
+    ((3, 2, 4), synth.configs.RC_SECOND, 0.8, 7, (250.0, 600.0, 1200.0)),
+    ((2, 2, 2), synth.configs.RC_SECOND, 1.3, 5, (300.0,)),
+    ((5, 1, 1), synth.configs.RC_FIRST, 1.0, 2, (300.0, 700.0)),
+    ((1, 1, 1), synth.configs.RC_SECOND, 1.0, 7, (300.0,)),
+])
+def test_ragged_grids_second_shell(fp4, grid, rc, sb, mask, T):
+    """Non-cubic and degenerate grids, second-shell FC4 (1522 quartets, 34 groups), several
+    temperatures and channel masks; sampled targets for the oracle."""
+    _say("case: ragged", grid, rc, sb, mask, T)
+    inst = synth.diamond_instance(grid, rc, seed=31, T=T)
+    rng = np.random.default_rng(1)
+    nm = inst.nmodes
+    targets = np.unique(np.concatenate([[0, nm - 1], rng.choice(nm, min(nm, 10), replace=False)]))
+    r_o, rch_o, c_o = _oracle(inst, T, sb, mask, targets)
+    with _ctx(fp4, inst) as c:
+        r, rch, cnt = c.compute_rates4(T, sb, mask, fp4.FP4_FP64, targets=targets, by_channel=True)
+        rall, _, call = c.compute_rates4(T, sb, mask, fp4.FP4_FP64)
+    assert np.array_equal(cnt, c_o)
+    assert _rel(r, r_o) <= RTOL64
+    assert _rel(rch, rch_o) <= RTOL64
+    # the subset entry point and the full-grid entry point agree bit for bit
+    assert np.array_equal(rall[:, targets], r)
+    assert np.array_equal(call[targets], cnt)
+
+
+def test_debug_matrix_elements(fp4):
+    """V through the library's own contraction (W'', F, E3 F E4^T) against Eq. V4 evaluated
+    literally by the oracle, all three channels, Umklapp included."""
+    _say("case: debug V")
+    inst = synth.diamond_instance((4, 4, 4), synth.configs.RC_SECOND, seed=7)
+    m = oracle.Model.from_instance(inst)
+    rng = np.random.default_rng(2)
+    pts = grid_points(inst.grid)
+    quads, modes, signs = [], [], []
+    for _ in range(60):
+        ch = int(rng.integers(0, 3))
+        s1, s2 = [(1, 1), (1, -1), (-1, -1)][ch]
+        iq, iq1, iq2 = (int(x) for x in rng.integers(0, inst.nq, 3))
+        j, j1, j2, j3 = (int(x) for x in rng.integers(0, inst.nb, 4))
+        iq3 = int(flat_index((pts[iq] + s1 * pts[iq1] + s2 * pts[iq2]) % np.asarray(inst.grid), inst.grid))
+        quads.append([iq, j, iq1, j1, iq2, j2, j3, ch])
+        modes.append([iq * 6 + j, iq1 * 6 + j1, iq2 * 6 + j2, iq3 * 6 + j3])
+        signs.append([1, s1, s2, -1])
+    V_o = oracle.v4(m, np.array(modes), np.array(signs))
+    with _ctx(fp4, inst) as c:
+        V64 = c.debug_matrix_elements(np.array(quads), fp4.FP4_FP64)
+        V32 = c.debug_matrix_elements(np.array(quads), fp4.FP4_FP32)
+    scale = np.max(np.abs(V_o))
+    assert np.max(np.abs(V64 - V_o)) <= 1e-12 * scale
+    assert np.max(np.abs(V32 - V_o)) <= 1e-5 * scale
+
+
+def test_closed_form_gamma_only(fp4):
+    """One atom at Gamma only (N = 1), hand-built modes: the HIP path reproduces the oracle
+    (which is pinned to the hand-enumerated closed form)."""
+    _say("case: gamma only")
+    import itertools
+    rng = np.random.default_rng(9)
+    C = rng.standard_normal((3, 3, 3, 3))
+    C = sum(np.transpose(C, p) for p in itertools.permutations(range(4))) / 24.0
+    w = np.array([[10.0, 20.0, 30.0]])
+    evec = np.zeros((1, 3, 1, 3), dtype=complex)
+    for j in range(3):
+        evec[0, j, 0, j] = 1.0
+    vel = np.zeros((1, 3, 3))
+    atoms = np.zeros((1, 4), dtype=np.int32)
+    cells = np.zeros((1, 3, 3), dtype=np.int32)
+    A = np.eye(3) * 3.0
+    mo = oracle.Model((1, 1, 1), [12.0], w, evec, vel, atoms, cells, C.reshape(1, 81))
+    r_o, _, c_o = oracle.rates4(mo, [400.0], 1.0, 7, 0.3)
+    with fp4.Context(0) as c:
+        c.load_lattice(A, (1, 1, 1), [12.0], 0.3)
+        c.load_modes(w, evec, vel)
+        c.load_fc4(atoms, cells, C.reshape(1, 81))
+        r, _, cnt = c.compute_rates4([400.0], 1.0, 7, fp4.FP4_FP64)
+    assert np.array_equal(cnt, c_o)
+    assert _rel(r, r_o) <= RTOL64
+
+
+def test_properties_on_gpu(fp4, small):
+    """Invariants that hold at any size, checked on the HIP path itself: time reversal
+    (counts equal, rates equal to rounding), mask additivity, exact x4 under Phi -> 2 Phi."""
+    _say("case: gpu properties")
+    mq = minus_index(small.grid)
+    with _ctx(fp4, small) as c:
+        r, rch, cnt = c.compute_rates4([300.0], 1.0, 7, fp4.FP4_FP64, by_channel=True)
+        parts = [c.compute_rates4([300.0], 1.0, 1 << ch, fp4.FP4_FP64) for ch in range(3)]
+    r = r[0].reshape(small.nq, small.nb)
+    assert np.array_equal(cnt.reshape(small.nq, small.nb, 3), cnt.reshape(small.nq, small.nb, 3)[mq])
+    np.testing.assert_allclose(r[mq], r, rtol=1e-13)
+    for ch in range(3):
+        np.testing.assert_allclose(parts[ch][0][0], rch[0, ch], rtol=1e-14)
+        assert np.array_equal(parts[ch][2][:, ch], cnt[:, ch])
+    with _ctx(fp4, small, phi_scale=2.0) as c:
+        r2, _, cnt2 = c.compute_rates4([300.0], 1.0, 7, fp4.FP4_FP64)
+    assert np.array_equal(cnt2.reshape(small.nq, small.nb, 3), cnt.reshape(small.nq, small.nb, 3))
+    assert np.array_equal(r2[0].reshape(small.nq, small.nb), 4.0 * r)
+
+
+def test_error_paths(fp4, small):
+    """Documented error codes; the context stays usable afterwards."""
+    _say("case: error paths")
+    import ctypes
+    with fp4.Context(0) as c:
+        T = np.array([300.0])
+        out = np.zeros(small.nmodes)
+        P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        assert c.call("fp4_compute_rates4", P(T), 1, 1.0, 7, 0, P(out), None, None) == fp4.FP4_E_STATE
+        c.load_instance(small)
+        assert c.call("fp4_compute_rates4", P(T), 1, 1.0, 0, 0, P(out), None, None) == fp4.FP4_E_INVAL
+        assert c.call("fp4_compute_rates4", P(T), 1, -1.0, 7, 0, P(out), None, None) == fp4.FP4_E_INVAL
+        bad = np.array([-3.0])
+        assert c.call("fp4_compute_rates4", P(bad), 1, 1.0, 7, 0, P(out), None, None) == fp4.FP4_E_INVAL
+        assert c.call("fp4_compute_rates4", P(T), 1, 1.0, 7, 9, P(out), None, None) == fp4.FP4_E_UNSUPPORTED
+        assert c.call("fp4_compute_rates4", P(T), 9, 1.0, 7, 0, P(out), None, None) == fp4.FP4_E_INVAL
+        om = small.omega.copy()
+        om[3, 2] = np.nan
+        with pytest.raises(fp4.Fp4Error) as e:
+            c.load_modes(om, small.evec, small.vel)
+        assert e.value.code == fp4.FP4_E_INVAL
+        at = small.fc4.atoms.copy()
+        at[0, 2] = 5
+        with pytest.raises(fp4.Fp4Error) as e:
+            c.load_fc4(at, small.fc4.cells, small.fc4.phi)
+        assert e.value.code == fp4.FP4_E_INVAL
+        tg = np.array([0, small.nmodes], dtype=np.int32)
+        with pytest.raises(fp4.Fp4Error):
+            c.compute_rates4([300.0], targets=tg)
+        # still usable
+        r, _, cnt = c.compute_rates4([300.0], 1.0, 7, fp4.FP4_FP64, targets=[5])
+        assert cnt.sum() > 0 and r[0, 0] > 0
+
+
+def test_medium_full_size_sampled(fp4):
+    """The 8x8x8 second-shell workload at full size, two temperatures, in the launch
+    configuration the benchmark times: counts of 48 sampled modes bit-exact, complete rates
+    of one mode against the oracle, the recombination and splitting channels of three more
+    modes, FP32 within 1e-4 on the same modes, and time reversal on the whole grid."""
+    _say("case: medium 8x8x8 full size")
+    inst = synth.medium()
+    rng = np.random.default_rng(4)
+    sample = rng.choice(np.arange(3, inst.nmodes), 48, replace=False)
+    with _ctx(fp4, inst) as c:
+        r, rch, cnt = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64, by_channel=True)
+        r32, _, cnt32 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP32)
+    assert np.array_equal(cnt32, cnt)
+    _, _, c_o = _oracle(inst, inst.T, 1.0, 7, sample, want_rates=False)
+    assert np.array_equal(cnt[sample], c_o)
+    mq = minus_index(inst.grid)
+    rr = r.reshape(len(inst.T), inst.nq, inst.nb)
+    np.testing.assert_allclose(rr[:, mq], rr, rtol=1e-12)
+    side = sample[:3]
+    r_o, rch_o, _ = _oracle(inst, inst.T, 1.0, 5, side)
+    assert _rel(rch[:, 0][:, side], rch_o[:, 0]) <= RTOL64
+    assert _rel(rch[:, 2][:, side], rch_o[:, 2]) <= RTOL64
+    one = sample[3:4]
+    _say("oracle: one full mode of the 8x8x8 workload")
+    r_o, _, _ = _oracle(inst, inst.T, 1.0, 7, one)
+    assert _rel(r[:, one], r_o) <= RTOL64
+    assert _rel(r32[:, one], r_o) <= RTOL32
