@@ -23,6 +23,7 @@ struct Crystal {
   const double *omega;      // [N*nb]
   const double *inv_omega;  // [N*nb] 1/omega (0 for inactive modes)
   const double4 *vel;       // [N*nb] (x, y, z, 0)
+  const double4 *mode4;     // [N*nb] (vx, vy, vz, omega)
   const double2 *E64;       // [N][nb][nb]  e_{j}(atom, x) / sqrt(M_atom), column = 3 atom + x
   const float2 *E32;        // same, FP32
   const int4 *qn;           // [N] (n1, n2, n3, 0)
@@ -63,7 +64,7 @@ struct RateArgs {
 };
 
 // launchers (fp4_kernels.hip)
-hipError_t launch_tables(const Crystal &c, double *inv_omega, double2 *E64, float2 *E32,
+hipError_t launch_tables(const Crystal &c, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec, hipStream_t s);

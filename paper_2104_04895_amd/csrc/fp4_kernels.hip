@@ -81,6 +81,12 @@ __device__ __forceinline__ int wrap(int x, int g) {
   return x;
 }
 
+// Keep a complex value in registers at this point of the instruction stream: the arithmetic
+// that produces it cannot sink below, and (with the memory clobber) later loads cannot be
+// hoisted above.  Used to bound the number of LDS rows in flight in the branch-block products.
+__device__ __forceinline__ void pin(double2 &v) { __asm__ volatile("" : "+v"(v.x), "+v"(v.y)::"memory"); }
+__device__ __forceinline__ void pin(float2 &v) { __asm__ volatile("" : "+v"(v.x), "+v"(v.y)::"memory"); }
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -107,7 +113,7 @@ __device__ __forceinline__ double add_signed(double a, double b, int s) {
 
 // ------------------------------------------------------------------ table kernels
 
-__global__ void k_tables(Crystal c, double *inv_omega, double2 *E64, float2 *E32,
+__global__ void k_tables(Crystal c, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec) {
@@ -119,6 +125,8 @@ __global__ void k_tables(Crystal c, double *inv_omega, double2 *E64, float2 *E32
   for (int j = 0; j < nb; ++j) {
     const double w = c.omega[(size_t)iq * nb + j];
     inv_omega[(size_t)iq * nb + j] = w > 0.0 ? 1.0 / w : 0.0;
+    const double4 v = c.vel[(size_t)iq * nb + j];
+    mode4[(size_t)iq * nb + j] = make_double4(v.x, v.y, v.z, w);
   }
   for (int j = 0; j < nb; ++j)
     for (int col = 0; col < nb; ++col) {
@@ -230,11 +238,22 @@ __device__ void build_W(const Crystal &c, const typename CT<R>::T *Ut, int iq1, 
 template <typename R, int NB, int S2>
 __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>::T *Ws,
                                           int iq2, int iq3, int r,
-                                          typename CT<R>::T *Xg, typename CT<R>::T (&V)[NB]) {
+                                          typename CT<R>::T *Xg, typename CT<R>::T *Pg,
+                                          const int *sg_d, const int *skl,
+                                          typename CT<R>::T (&V)[NB]) {
   using CR = typename CT<R>::T;
   constexpr int NAT = NB / 3;
   const int k = r / 3, gam = r - 3 * k;
-  const CR *phd = PHDtab<R>(c) + (size_t)iq2 * c.nd;
+  // stage exp(i s'' q''.d) of every distinct d in the group's phase tile
+  {
+    const CR *phd = PHDtab<R>(c) + (size_t)iq2 * c.nd;
+    for (int i = r; i < c.nd; i += NB) {
+      CR ph = phd[i];
+      if (S2 < 0) ph = cconj(ph);
+      Pg[i] = ph;
+    }
+  }
+  wave_sync();
   // F row r, accumulated in the atom order l = k, k+1, ... (mod NAT) so that the
   // register index is static
   CR Frel[NB];
@@ -243,10 +262,9 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
 #pragma unroll
   for (int rl = 0; rl < NAT; ++rl) {
     const int l = (k + rl) % NAT;
-    const int gb = c.kl_start[k * NAT + l], ge = c.kl_start[k * NAT + l + 1];
+    const int gb = skl[k * NAT + l], ge = skl[k * NAT + l + 1];
     for (int g = gb; g < ge; ++g) {
-      CR ph = phd[c.g_d[g]];
-      if (S2 < 0) ph = cconj(ph);
+      const CR ph = Pg[sg_d[g]];
       const CR *wg = Ws + g * 9 + gam * 3;
 #pragma unroll
       for (int th = 0; th < 3; ++th) cmac(Frel[rl * 3 + th], ph, wg[th]);
@@ -276,7 +294,8 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
     if (S2 < 0) e = cconj(e);
 #pragma unroll
     for (int col = 0; col < NB; ++col) cmac(H[col], e, Xg[kg * NB + col]);
-    __asm__ volatile("" ::: "memory");   // bound the number of tile rows in flight
+#pragma unroll
+    for (int col = 0; col < NB; ++col) pin(H[col]);
   }
   wave_sync();
   // E4 rows: lane r writes row r = conj(E[q'''][r][:])
@@ -289,8 +308,8 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
     CR v = czero<CR>();
 #pragma unroll
     for (int col = 0; col < NB; ++col) cmac(v, H[col], Xg[cc * NB + col]);
+    pin(v);
     V[cc] = v;
-    __asm__ volatile("" ::: "memory");
   }
   wave_sync();
 }
@@ -310,7 +329,8 @@ template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs &a,
                                                const typename CT<R>::T *W, int G, int NGRP,
                                                int gw, int r, typename CT<R>::T *Xg,
-                                               int4 nq, int4 nq1, int mu, int mu1, double w,
+                                               typename CT<R>::T *Pg, const int *sg_d,
+                                               const int *skl, int4 nq, int4 nq1, int mu, int mu1, double w,
                                                double w1, const double (&invn)[NT],
                                                const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
@@ -329,17 +349,16 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
     const int iq3 = x + c.g0 * (y + c.g1 * z);
     // FP64 window prefilter of this lane's row (j'' = r) against every j'''
     const int mu2 = iq2 * NB + r;
-    const double w2 = c.omega[mu2];
-    const double4 v2 = c.vel[mu2];
+    const double4 v2 = c.mode4[mu2];
+    const double w2 = v2.w;
     const double bw = add_signed(aw, w2, S2);
     unsigned bits = 0;
     if (w2 > 0.0) {
 #pragma unroll 2
       for (int cc = 0; cc < NB; ++cc) {
-        const int mu3 = iq3 * NB + cc;
-        const double w3 = c.omega[mu3];
+        const double4 v3 = c.mode4[iq3 * NB + cc];
         double dw, s2;
-        if (w3 > 0.0 && window_keep(bw, w3, v2, c.vel[mu3], a.c_win, dw, s2)) bits |= 1u << cc;
+        if (v3.w > 0.0 && window_keep(bw, v3.w, v2, v3, a.c_win, dw, s2)) bits |= 1u << cc;
       }
     }
     const unsigned long long bal = __ballot(bits != 0u);
@@ -347,7 +366,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
     if (gbits == 0ull) continue;           // no surviving process in this branch block
     if (r == 0) acc.blocks += 1;
     CR V[NB];
-    block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, V);
+    block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
     if (bits == 0u) continue;
     // the lane's row of V goes through its own row of the group tile, so that the
     // survivor loop below is not unrolled
@@ -361,9 +380,10 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
     for (int cc = 0; cc < NB; ++cc) {
       if (!((bits >> cc) & 1u)) continue;
       const int mu3 = iq3 * NB + cc;
-      const double w3 = c.omega[mu3];
+      const double4 v3 = c.mode4[mu3];
+      const double w3 = v3.w;
       double dw, s2;
-      window_keep(bw, w3, v2, c.vel[mu3], a.c_win, dw, s2);
+      window_keep(bw, w3, v2, v3, a.c_win, dw, s2);
       const CR vv = Xg[r * NB + cc];
       const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
       const double sig2 = a.c_sig * s2;
@@ -398,12 +418,18 @@ __global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   CR *W = reinterpret_cast<CR *>(smem);                 // [2][ng][9]
   CR *X = W + 2 * c.ng * 9;                             // [NGRP][NB][NB]
+  CR *P = X + NGRP * NB * NB;                           // [NGRP][nd]
+  int *sg_d = reinterpret_cast<int *>(P + NGRP * c.nd); // [ng]
+  int *skl = sg_d + c.ng;                               // [nat*nat + 1]
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int gw = lane / NB, r = lane - gw * NB;
   const bool glane = gw < GPW;
   const int G = wave * GPW + gw;
   CR *Xg = X + (size_t)(glane ? G : 0) * NB * NB;
+  CR *Pg = P + (size_t)(glane ? G : 0) * c.nd;
+  for (int i = tid; i < c.ng; i += 256) sg_d[i] = c.g_d[i];
+  for (int i = tid; i <= c.nat * c.nat; i += 256) skl[i] = c.kl_start[i];
 
   const int t = blockIdx.x / a.nchunk, chunk = blockIdx.x - t * a.nchunk;
   const int mu = a.targets[t];
@@ -417,6 +443,7 @@ __global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
   }
   acc.blocks = 0;
   const double w = c.omega[mu];
+  __syncthreads();
   if (w > 0.0) {
     const int4 nq = c.qn[iq];
     const CR *Ut = reinterpret_cast<const CR *>(a.U) + (size_t)t * c.nc * 27;
@@ -439,11 +466,11 @@ __global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) n1[tt] = (tt < a.nT) ? a.occ[(size_t)tt * c.N * NB + mu1] : 0.0;
         if (a.mask & 1u)
-          channel_blocks<R, NB, NT, 0>(c, a, W, G, NGRP, gw, r, Xg, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 0>(c, a, W, G, NGRP, gw, r, Xg, Pg, sg_d, skl, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
         if (a.mask & 2u)
-          channel_blocks<R, NB, NT, 1>(c, a, W, G, NGRP, gw, r, Xg, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 1>(c, a, W, G, NGRP, gw, r, Xg, Pg, sg_d, skl, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
         if (a.mask & 4u)
-          channel_blocks<R, NB, NT, 2>(c, a, W, G, NGRP, gw, r, Xg, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 2>(c, a, W, G, NGRP, gw, r, Xg, Pg, sg_d, skl, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
       }
     }
   }
@@ -520,7 +547,12 @@ __global__ __launch_bounds__(64) void k_debug_v(Crystal c, const int *quads, con
   extern __shared__ __align__(16) unsigned char smem[];
   CR *W = reinterpret_cast<CR *>(smem);
   CR *Xg = W + 2 * c.ng * 9;
+  CR *Pg = Xg + NB * NB;
+  int *sg_d = reinterpret_cast<int *>(Pg + c.nd);
+  int *skl = sg_d + c.ng;
   const int p = blockIdx.x, tid = threadIdx.x;
+  for (int i = tid; i < c.ng; i += 64) sg_d[i] = c.g_d[i];
+  for (int i = tid; i <= c.nat * c.nat; i += 64) skl[i] = c.kl_start[i];
   const int *qd = quads + 8 * p;
   const int iq = qd[0], iq1 = qd[2], j1 = qd[3], iq2 = qd[4], j2 = qd[5], j3 = qd[6], ch = qd[7];
   const CR *Ut = U + (size_t)tslot[p] * c.nc * 27;
@@ -535,8 +567,8 @@ __global__ __launch_bounds__(64) void k_debug_v(Crystal c, const int *quads, con
   const int iq3 = x + c.g0 * (y + c.g1 * z);
   CR V[NB];
   const CR *Ws = W + (s1 > 0 ? 0 : c.ng * 9);
-  if (s2 > 0) block_row<R, NB, 1>(c, Ws, iq2, iq3, tid, Xg, V);
-  else block_row<R, NB, -1>(c, Ws, iq2, iq3, tid, Xg, V);
+  if (s2 > 0) block_row<R, NB, 1>(c, Ws, iq2, iq3, tid, Xg, Pg, sg_d, skl, V);
+  else block_row<R, NB, -1>(c, Ws, iq2, iq3, tid, Xg, Pg, sg_d, skl, V);
   if (tid == j2) {
 #pragma unroll
     for (int cc = 0; cc < NB; ++cc)
@@ -553,7 +585,9 @@ template <typename R, int NB, int NT>
 hipError_t launch_rates_t(const Crystal &c, const RateArgs &a, hipStream_t s) {
   using CR = typename CT<R>::T;
   constexpr int GPW = 64 / NB;
-  const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB);
+  const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB +
+                                   (size_t)4 * GPW * c.nd) +
+                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1);
   const size_t lds_red = sizeof(double) * 4 * 3 * NT + sizeof(unsigned long long) * 16;
   const size_t bytes = lds > lds_red ? lds : lds_red;
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
@@ -585,7 +619,8 @@ template <typename R, int NB>
 hipError_t launch_debug_nb(const Crystal &c, const int *quads, int n, const int *tslot,
                            const void *U, double2 *V, hipStream_t s) {
   using CR = typename CT<R>::T;
-  const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)NB * NB);
+  const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)NB * NB + c.nd) +
+                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1);
   hipLaunchKernelGGL((k_debug_v<R, NB>), dim3(n), dim3(64), lds, s, c, quads, tslot,
                      reinterpret_cast<const CR *>(U), V);
   return hipGetLastError();
@@ -605,12 +640,12 @@ hipError_t launch_debug_r(const Crystal &c, const int *quads, int n, const int *
 
 }  // namespace
 
-hipError_t launch_tables(const Crystal &c, double *inv_omega, double2 *E64, float2 *E32,
+hipError_t launch_tables(const Crystal &c, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec, hipStream_t s) {
   const int nthr = 128;
-  hipLaunchKernelGGL(k_tables, dim3((c.N + nthr - 1) / nthr), dim3(nthr), 0, s, c, inv_omega, E64, E32,
+  hipLaunchKernelGGL(k_tables, dim3((c.N + nthr - 1) / nthr), dim3(nthr), 0, s, c, mode4, inv_omega, E64, E32,
                      evec, mass, qn, PHA64, PHB64, PHD64, PHD32, avec, bvec, dvec);
   return hipGetLastError();
 }
