@@ -70,7 +70,7 @@ struct fp4_ctx {
   std::vector<double> q_phi;
 
   // device buffers
-  DevBuf d_omega, d_iw, d_m4, d_vel, d_evec, d_mass, d_E64, d_E32, d_qn, d_PHA64, d_PHB64, d_PHD64, d_PHD32;
+  DevBuf d_omega, d_iw, d_m4, d_qbnd, d_vel, d_evec, d_mass, d_E64, d_E32, d_qn, d_PHA64, d_PHB64, d_PHD64, d_PHD32;
   DevBuf d_g_d, d_kl, d_cs, d_cj, d_ca, d_cq, d_qi, d_qb, d_qphi, d_avec, d_bvec, d_dvec;
   DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
   DevBuf d_rates, d_rch, d_counts, d_quads, d_tslot, d_V;
@@ -155,6 +155,7 @@ fp4::Crystal make_crystal(const fp4_ctx *ctx) {
   c.inv_omega = (const double *)ctx->d_iw.p;
   c.vel = (const double4 *)ctx->d_vel.p;
   c.mode4 = (const double4 *)ctx->d_m4.p;
+  c.qbound = (const double4 *)ctx->d_qbnd.p;
   c.E64 = (const double2 *)ctx->d_E64.p;
   c.E32 = (const float2 *)ctx->d_E32.p;
   c.qn = (const int4 *)ctx->d_qn.p;
@@ -181,6 +182,7 @@ int ensure_tables(fp4_ctx *ctx) {
   int rc;
   if ((rc = ensure(ctx, ctx->d_iw, N * nb * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->d_m4, N * nb * sizeof(double4)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_qbnd, N * sizeof(double4)))) return rc;
   if ((rc = ensure(ctx, ctx->d_E64, N * nb * nb * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx, ctx->d_E32, N * nb * nb * sizeof(float2)))) return rc;
   if ((rc = ensure(ctx, ctx->d_qn, N * sizeof(int4)))) return rc;
@@ -189,7 +191,7 @@ int ensure_tables(fp4_ctx *ctx) {
   if ((rc = ensure(ctx, ctx->d_PHD64, N * ctx->nd * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx, ctx->d_PHD32, N * ctx->nd * sizeof(float2)))) return rc;
   fp4::Crystal c = make_crystal(ctx);
-  FP4_HIP(ctx, fp4::launch_tables(c, (double4 *)ctx->d_m4.p, (double *)ctx->d_iw.p, (double2 *)ctx->d_E64.p, (float2 *)ctx->d_E32.p,
+  FP4_HIP(ctx, fp4::launch_tables(c, (double4 *)ctx->d_qbnd.p, (double4 *)ctx->d_m4.p, (double *)ctx->d_iw.p, (double2 *)ctx->d_E64.p, (float2 *)ctx->d_E32.p,
                                   (const double *)ctx->d_evec.p, (const double *)ctx->d_mass.p,
                                   (int4 *)ctx->d_qn.p, (double2 *)ctx->d_PHA64.p,
                                   (double2 *)ctx->d_PHB64.p, (double2 *)ctx->d_PHD64.p,
@@ -252,6 +254,7 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
   fp4::RateArgs a{};
   const double wsb = ctx->window_w * sb;
   a.c_win = (wsb * ctx->dq) * (wsb * ctx->dq);
+  a.sqrt_c_win = wsb * ctx->dq;
   a.c_sig = (sb * ctx->dq) * (sb * ctx->dq);
   a.c_min = ctx->sigma_min * ctx->sigma_min;
   a.kpref = c4_prefactor() / ((double)ctx->N * (double)ctx->N);
@@ -432,7 +435,7 @@ void fp4_destroy(fp4_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
+  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_qbnd, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
                    &ctx->d_E32, &ctx->d_qn, &ctx->d_PHA64, &ctx->d_PHB64, &ctx->d_PHD64,
                    &ctx->d_PHD32, &ctx->d_g_d, &ctx->d_kl, &ctx->d_cs, &ctx->d_cj, &ctx->d_ca,
                    &ctx->d_cq, &ctx->d_qi, &ctx->d_qb, &ctx->d_qphi, &ctx->d_avec, &ctx->d_bvec,

@@ -24,6 +24,7 @@ struct Crystal {
   const double *inv_omega;  // [N*nb] 1/omega (0 for inactive modes)
   const double4 *vel;       // [N*nb] (x, y, z, 0)
   const double4 *mode4;     // [N*nb] (vx, vy, vz, omega)
+  const double4 *qbound;    // [N] (min omega, max omega, max |v|, 0) of the active branches
   const double2 *E64;       // [N][nb][nb]  e_{j}(atom, x) / sqrt(M_atom), column = 3 atom + x
   const float2 *E32;        // same, FP32
   const int4 *qn;           // [N] (n1, n2, n3, 0)
@@ -45,6 +46,7 @@ struct Crystal {
 // Per-call parameters of the rate kernel.
 struct RateArgs {
   double c_win;             // ((W sb) dq)^2 : keep <=> dw^2 <= c_win s2
+  double sqrt_c_win;        // W sb dq
   double c_sig;             // (sb dq)^2     : sigma^2 = c_sig s2
   double c_min;             // sigma_min^2   : delta := 1 below
   double kpref;             // C4 / N^2
@@ -64,7 +66,7 @@ struct RateArgs {
 };
 
 // launchers (fp4_kernels.hip)
-hipError_t launch_tables(const Crystal &c, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
+hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec, hipStream_t s);

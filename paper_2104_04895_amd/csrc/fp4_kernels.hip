@@ -113,7 +113,7 @@ __device__ __forceinline__ double add_signed(double a, double b, int s) {
 
 // ------------------------------------------------------------------ table kernels
 
-__global__ void k_tables(Crystal c, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
+__global__ void k_tables(Crystal c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec) {
@@ -127,6 +127,20 @@ __global__ void k_tables(Crystal c, double4 *mode4, double *inv_omega, double2 *
     inv_omega[(size_t)iq * nb + j] = w > 0.0 ? 1.0 / w : 0.0;
     const double4 v = c.vel[(size_t)iq * nb + j];
     mode4[(size_t)iq * nb + j] = make_double4(v.x, v.y, v.z, w);
+  }
+  // frequency range and largest speed of the active branches at this q (an empty range,
+  // w_min > w_max, when no branch is active)
+  {
+    double wmin = 1e300, wmax = -1e300, vmax = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      const double w = c.omega[(size_t)iq * nb + j];
+      if (!(w > 0.0)) continue;
+      const double4 v = c.vel[(size_t)iq * nb + j];
+      wmin = fmin(wmin, w);
+      wmax = fmax(wmax, w);
+      vmax = fmax(vmax, sqrt(v.x * v.x + v.y * v.y + v.z * v.z));
+    }
+    qbound[iq] = make_double4(wmin, wmax, vmax, 0.0);
   }
   for (int j = 0; j < nb; ++j)
     for (int col = 0; col < nb; ++col) {
@@ -323,90 +337,182 @@ struct Acc {
   unsigned blocks;
 };
 
-// All blocks (q'') of one channel for fixed lambda, lambda'.  Group G of the work-group
-// handles q'' = G, G + NGRP, ...; lane r of the group owns branch row j'' = r.
+// Window-prefilter bits of one row of a branch block.  Lane r owns row mode mu_r = (q'', r);
+// column cc is (q''', cc).  orient 0 tests the processes (lambda'' = row, lambda''' = column),
+// orient 1 the mirrored ones (lambda'' = column, lambda''' = row) of the redistribution
+// channel.  Each candidate is evaluated in the same FP64 order as a stand-alone process.
+//
+// A row is skipped without testing its candidates when no candidate can pass: dw of the row
+// lies in x - [w_min, w_max] of q''' (active branches) and a kept process needs
+// |dw| <= sqrt(c_win) |v'' - v'''| <= sqrt(c_win) (|v_row| + v_max(q''')); the bound is
+// applied with a relative margin of 1e-6, far above FP64 rounding, so it never drops a
+// process the exact test would keep.
+template <int NB, int S2>
+__device__ __forceinline__ unsigned row_bits(const Crystal &c, const RateArgs &a, double aw,
+                                             int mur, int iqc, int orient) {
+  const double4 vr = c.mode4[mur];
+  if (!(vr.w > 0.0)) return 0u;
+  {
+    const double4 qb = c.qbound[iqc];   // (w_min, w_max, v_max, sqrt(0)) over active branches
+    const double x = orient == 0 ? add_signed(aw, vr.w, S2) : aw - vr.w;
+    const double lo = x - qb.y, hi = x - qb.x;
+    const double dist = lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0);
+    const double speed = sqrt(vr.x * vr.x + vr.y * vr.y + vr.z * vr.z);
+    if (dist > a.sqrt_c_win * (speed + qb.z) * (1.0 + 1e-6) + 1e-12) return 0u;
+  }
+  unsigned bits = 0u;
+  if (orient == 0) {
+    const double bw = add_signed(aw, vr.w, S2);
+#pragma unroll 2
+    for (int cc = 0; cc < NB; ++cc) {
+      const double4 vc = c.mode4[iqc * NB + cc];
+      double dw, s2;
+      if (vc.w > 0.0 && window_keep(bw, vc.w, vr, vc, a.c_win, dw, s2)) bits |= 1u << cc;
+    }
+  } else {
+#pragma unroll 2
+    for (int cc = 0; cc < NB; ++cc) {
+      const double4 vc = c.mode4[iqc * NB + cc];
+      double dw, s2;
+      if (vc.w > 0.0 && window_keep(add_signed(aw, vc.w, S2), vr.w, vc, vr, a.c_win, dw, s2))
+        bits |= 1u << cc;
+    }
+  }
+  return bits;
+}
+
+// Gamma (Eq. 4phgamma) of the kept processes of one row and orientation, accumulated into
+// the lane's FP64 partial rates.  Vrow[cc] is V of the row's process with column cc.
+template <typename R, int NB, int NT, int CH>
+__device__ __forceinline__ void gamma_row(const Crystal &c, const RateArgs &a,
+                                          const typename CT<R>::T *Vrow, unsigned bits,
+                                          int orient, int mur, int iqc, double aw, double kw,
+                                          const double (&invn)[NT], const double (&n1)[NT],
+                                          Acc<NT> &acc) {
+  using CR = typename CT<R>::T;
+  constexpr int S2 = (CH == 0) ? 1 : -1;
+#pragma unroll 1
+  for (int cc = 0; cc < NB; ++cc) {
+    if (!((bits >> cc) & 1u)) continue;
+    const int muc = iqc * NB + cc;
+    const int mu2 = orient == 0 ? mur : muc;
+    const int mu3 = orient == 0 ? muc : mur;
+    const double4 v2 = c.mode4[mu2];
+    const double4 v3 = c.mode4[mu3];
+    double dw, s2;
+    window_keep(add_signed(aw, v2.w, S2), v3.w, v2, v3, a.c_win, dw, s2);
+    const CR vv = Vrow[cc];
+    const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
+    const double sig2 = a.c_sig * s2;
+    double delta = 1.0;
+    if (!(sig2 < a.c_min)) {
+      // adaptive Gaussian, 1/sqrt(pi) = 0.5641895835477563
+      const double is2 = 1.0 / sig2;
+      delta = exp(-(dw * dw) * is2) * (0.5641895835477563 * sqrt(is2));
+    }
+    const double base = kw * c.inv_omega[mu2] * c.inv_omega[mu3] * v2abs * delta;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t < a.nT) {
+        const double n2 = a.occ[(size_t)t * c.N * NB + mu2];
+        const double n3 = a.occ[(size_t)t * c.N * NB + mu3];
+        double f;
+        if (CH == 0) f = (1.0 + n1[t]) * (1.0 + n2) * n3;
+        else if (CH == 1) f = (1.0 + n1[t]) * n2 * n3;
+        else f = n1[t] * n2 * n3;
+        acc.r[CH][t] += base * f * invn[t];
+      }
+    }
+    acc.cnt[CH] += 1;
+  }
+}
+
+constexpr int QSEG = 512;   // q'' points a wavefront queues at a time
+
+// All blocks (q'') of one channel for fixed lambda, lambda'.  Each wavefront owns a quarter
+// of the q'' points.  Phase 1 compacts the blocks worth contracting into the wavefront's LDS
+// queue in a fixed order (ballot + prefix count): for ++ and -- the blocks with a surviving
+// process, for +- one block of every mirror pair {q'', q'''} (V of the pair members are
+// transposes of each other).  Phase 2 lets the wavefront's lane groups contract the queued
+// blocks densely; lane r of a group owns branch row j'' = r.
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs &a,
-                                               const typename CT<R>::T *W, int G, int NGRP,
-                                               int gw, int r, typename CT<R>::T *Xg,
-                                               typename CT<R>::T *Pg, const int *sg_d,
-                                               const int *skl, int4 nq, int4 nq1, int mu, int mu1, double w,
+                                               const typename CT<R>::T *W, int wave, int lane,
+                                               int gw, int r, bool glane,
+                                               typename CT<R>::T *Xg, typename CT<R>::T *Pg,
+                                               const int *sg_d, const int *skl, int *Qw,
+                                               int4 nq, int4 nq1, int mu, int mu1, double w,
                                                double w1, const double (&invn)[NT],
                                                const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
+  constexpr int GPW = 64 / NB;
   constexpr int S1 = (CH == 2) ? -1 : 1;
   constexpr int S2 = (CH == 0) ? 1 : -1;
+  constexpr bool MIRROR = (CH == 1);
   constexpr double WCH = (CH == 2) ? (1.0 / 6.0) : 0.5;
+  constexpr unsigned long long GMASK = (1ull << NB) - 1ull;
   const CR *Ws = W + (S1 > 0 ? 0 : c.ng * 9);
   const double aw = add_signed(w, w1, S1);
   // weight of the channel (Eq. tao0), prefactor C4/N^2 and 1/(w w') of Eq. 4phgamma
   const double kw = WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
-  for (int iq2 = G; iq2 < c.N; iq2 += NGRP) {
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  auto fold3 = [&](int iq2) {
     const int4 nq2 = c.qn[iq2];
     const int x = wrap(nq.x + S1 * nq1.x + S2 * nq2.x, c.g0);
     const int y = wrap(nq.y + S1 * nq1.y + S2 * nq2.y, c.g1);
     const int z = wrap(nq.z + S1 * nq1.z + S2 * nq2.z, c.g2);
-    const int iq3 = x + c.g0 * (y + c.g1 * z);
-    // FP64 window prefilter of this lane's row (j'' = r) against every j'''
-    const int mu2 = iq2 * NB + r;
-    const double4 v2 = c.mode4[mu2];
-    const double w2 = v2.w;
-    const double bw = add_signed(aw, w2, S2);
-    unsigned bits = 0;
-    if (w2 > 0.0) {
-#pragma unroll 2
-      for (int cc = 0; cc < NB; ++cc) {
-        const double4 v3 = c.mode4[iq3 * NB + cc];
-        double dw, s2;
-        if (v3.w > 0.0 && window_keep(bw, v3.w, v2, v3, a.c_win, dw, s2)) bits |= 1u << cc;
-      }
-    }
-    const unsigned long long bal = __ballot(bits != 0u);
-    const unsigned long long gbits = (bal >> (gw * NB)) & ((1ull << NB) - 1ull);
-    if (gbits == 0ull) continue;           // no surviving process in this branch block
-    if (r == 0) acc.blocks += 1;
-    CR V[NB];
-    block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
-    if (bits == 0u) continue;
-    // the lane's row of V goes through its own row of the group tile, so that the
-    // survivor loop below is not unrolled
-#pragma unroll
-    for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
-    const double kw2 = kw * c.inv_omega[mu2];
-    double n2[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) n2[t] = (t < a.nT) ? a.occ[(size_t)t * c.N * NB + mu2] : 0.0;
-#pragma unroll 1
-    for (int cc = 0; cc < NB; ++cc) {
-      if (!((bits >> cc) & 1u)) continue;
-      const int mu3 = iq3 * NB + cc;
-      const double4 v3 = c.mode4[mu3];
-      const double w3 = v3.w;
-      double dw, s2;
-      window_keep(bw, w3, v2, v3, a.c_win, dw, s2);
-      const CR vv = Xg[r * NB + cc];
-      const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
-      const double sig2 = a.c_sig * s2;
-      double delta = 1.0;
-      if (!(sig2 < a.c_min)) {
-        // adaptive Gaussian, 1/sqrt(pi) = 0.5641895835477563
-        const double is2 = 1.0 / sig2;
-        delta = exp(-(dw * dw) * is2) * (0.5641895835477563 * sqrt(is2));
-      }
-      const double base = kw2 * c.inv_omega[mu3] * v2abs * delta;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if (t < a.nT) {
-          const double n3 = a.occ[(size_t)t * c.N * NB + mu3];
-          double f;
-          if (CH == 0) f = (1.0 + n1[t]) * (1.0 + n2[t]) * n3;
-          else if (CH == 1) f = (1.0 + n1[t]) * n2[t] * n3;
-          else f = n1[t] * n2[t] * n3;
-          acc.r[CH][t] += base * f * invn[t];
+    return x + c.g0 * (y + c.g1 * z);
+  };
+  // q'' is dealt to the wavefronts in rounds of GPW consecutive points, so that every
+  // wavefront sees the whole range (the mirror-pair members are not spread evenly over it)
+  const int nk = (c.N + 4 * GPW - 1) / (4 * GPW);
+  constexpr int KSEG = QSEG / GPW;
+  for (int k0 = 0; k0 < nk; k0 += KSEG) {
+    const int k1 = min(nk, k0 + KSEG);
+    // phase 1: queue
+    int cnt = 0;
+    for (int k = k0; k < k1; ++k) {
+      const int iq2 = (k * 4 + wave) * GPW + gw;
+      bool keep = false;
+      if (glane && iq2 < c.N) {
+        const int iq3 = fold3(iq2);
+        if (MIRROR) {
+          keep = iq2 <= iq3;
+        } else {
+          const unsigned bits = row_bits<NB, S2>(c, a, aw, iq2 * NB + r, iq3, 0);
+          const unsigned long long bal = __ballot(bits != 0u);
+          keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
         }
       }
-      acc.cnt[CH] += 1;
+      const bool lead = keep && r == 0;
+      const unsigned long long lb = __ballot(lead);
+      if (lead) Qw[cnt + __popcll(lb & lt)] = iq2;
+      cnt += __popcll(lb);
     }
+    wave_sync();
+    // phase 2: contract the queued blocks
+    if (glane) {
+      for (int e = gw; e < cnt; e += GPW) {
+        const int iq2 = Qw[e];
+        const int iq3 = fold3(iq2);
+        const int mur = iq2 * NB + r;
+        const unsigned bA = row_bits<NB, S2>(c, a, aw, mur, iq3, 0);
+        const unsigned bB = (MIRROR && iq2 != iq3) ? row_bits<NB, S2>(c, a, aw, mur, iq3, 1) : 0u;
+        const unsigned long long bal = __ballot((bA | bB) != 0u);
+        if (((bal >> (gw * NB)) & GMASK) == 0ull) continue;   // nothing survives in the block
+        if (r == 0) acc.blocks += 1;
+        CR V[NB];
+        block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
+        if ((bA | bB) == 0u) continue;
+        // the lane's row of V goes through its own row of the group tile, so that the
+        // survivor loop is not unrolled
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
+        if (bA) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bA, 0, mur, iq3, aw, kw, invn, n1, acc);
+        if (bB) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bB, 1, mur, iq3, aw, kw, invn, n1, acc);
+      }
+    }
+    wave_sync();
   }
 }
 
@@ -421,6 +527,7 @@ __global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
   CR *P = X + NGRP * NB * NB;                           // [NGRP][nd]
   int *sg_d = reinterpret_cast<int *>(P + NGRP * c.nd); // [ng]
   int *skl = sg_d + c.ng;                               // [nat*nat + 1]
+  int *Q = skl + c.nat * c.nat + 1;                     // [4][QSEG] block queues
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int gw = lane / NB, r = lane - gw * NB;
@@ -428,6 +535,7 @@ __global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
   const int G = wave * GPW + gw;
   CR *Xg = X + (size_t)(glane ? G : 0) * NB * NB;
   CR *Pg = P + (size_t)(glane ? G : 0) * c.nd;
+  int *Qw = Q + wave * QSEG;
   for (int i = tid; i < c.ng; i += 256) sg_d[i] = c.g_d[i];
   for (int i = tid; i <= c.nat * c.nat; i += 256) skl[i] = c.kl_start[i];
 
@@ -461,16 +569,15 @@ __global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
         __syncthreads();
         build_W<R>(c, Ut, iq1, j1, W, tid, 256);
         __syncthreads();
-        if (!glane) continue;
         double n1[NT];
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) n1[tt] = (tt < a.nT) ? a.occ[(size_t)tt * c.N * NB + mu1] : 0.0;
         if (a.mask & 1u)
-          channel_blocks<R, NB, NT, 0>(c, a, W, G, NGRP, gw, r, Xg, Pg, sg_d, skl, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 0>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
         if (a.mask & 2u)
-          channel_blocks<R, NB, NT, 1>(c, a, W, G, NGRP, gw, r, Xg, Pg, sg_d, skl, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 1>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
         if (a.mask & 4u)
-          channel_blocks<R, NB, NT, 2>(c, a, W, G, NGRP, gw, r, Xg, Pg, sg_d, skl, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 2>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
       }
     }
   }
@@ -587,7 +694,7 @@ hipError_t launch_rates_t(const Crystal &c, const RateArgs &a, hipStream_t s) {
   constexpr int GPW = 64 / NB;
   const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB +
                                    (size_t)4 * GPW * c.nd) +
-                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1);
+                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1 + 4 * QSEG);
   const size_t lds_red = sizeof(double) * 4 * 3 * NT + sizeof(unsigned long long) * 16;
   const size_t bytes = lds > lds_red ? lds : lds_red;
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
@@ -640,12 +747,12 @@ hipError_t launch_debug_r(const Crystal &c, const int *quads, int n, const int *
 
 }  // namespace
 
-hipError_t launch_tables(const Crystal &c, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
+hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec, hipStream_t s) {
   const int nthr = 128;
-  hipLaunchKernelGGL(k_tables, dim3((c.N + nthr - 1) / nthr), dim3(nthr), 0, s, c, mode4, inv_omega, E64, E32,
+  hipLaunchKernelGGL(k_tables, dim3((c.N + nthr - 1) / nthr), dim3(nthr), 0, s, c, qbound, mode4, inv_omega, E64, E32,
                      evec, mass, qn, PHA64, PHB64, PHD64, PHD32, avec, bvec, dvec);
   return hipGetLastError();
 }
