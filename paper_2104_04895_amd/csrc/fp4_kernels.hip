@@ -517,7 +517,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
 }
 
 template <typename R, int NB, int NT>
-__global__ __launch_bounds__(256, 2) void k_rates(Crystal c, RateArgs a) {
+__global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
   using CR = typename CT<R>::T;
   constexpr int GPW = 64 / NB;
   constexpr int NGRP = 4 * GPW;
