@@ -26,12 +26,12 @@ PEAK_FP32_VALU = 157.3e12
 
 def algorithmic_flops(stats, inst, n_pairs):
     """Algorithmic FLOPs of one main-kernel launch (per-unit figures in the design doc):
-    prefilter 12 per candidate, W'' build 456 per combo per (lambda, lambda') pair,
-    branch block 72 ng + 16 nb^3 per contracted block, Gamma 40 + 6 nT per kept process."""
-    from paper_2104_04895_amd import Context  # noqa: F401  (binding only)
+    W'' build 456 per combo per (lambda, lambda') pair, branch block 72 ng + 16 nb^3 per
+    contracted block, Gamma 40 + 6 nT per kept process (the per-candidate window test is
+    not credited)."""
     ng, nc, nb = inst["ng"], inst["nc"], inst["nb"]
     nT = inst["nT"]
-    return (12.0 * stats["candidates"] + 456.0 * nc * n_pairs
+    return (456.0 * nc * n_pairs
             + (72.0 * ng + 16.0 * nb ** 3) * stats["blocks"]
             + (40.0 + 6.0 * nT) * stats["processes"])
 
