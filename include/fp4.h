@@ -64,6 +64,7 @@ extern "C" {
 #define FP4_MM 4u
 
 typedef struct fp4_ctx fp4_ctx;
+typedef struct fp4_batch fp4_batch;
 
 /* Create a context on HIP device `device_id`.  *out receives the handle (NULL on error).
  * Returns FP4_E_DEVICE if the device cannot be used. */
@@ -75,7 +76,7 @@ void fp4_destroy(fp4_ctx *ctx);
 /* Lattice and grid (Sec. 2.2: N is the number of grid points).
  *   A[9]      lattice vectors as rows, Angstrom (non-singular)
  *   grid[3]   N1, N2, N3 >= 1, N = N1 N2 N3 <= 2^20
- *   natoms    1..16 atoms in the cell; nb = 3*natoms branches
+ *   natoms    1..4 atoms in the cell (nb = 3*natoms branches); more gives FP4_E_UNSUPPORTED
  *   mass      [natoms] amu, > 0
  *   dq        |Delta q''| of the adaptive broadening (App. B), 1/Angstrom; <= 0 selects
  *             (|det B|/N)^(1/3), the cube root of the reciprocal volume per grid point.
@@ -154,6 +155,51 @@ int fp4_last_stats(const fp4_ctx *ctx, int64_t *processes, int64_t *candidates,
  * recorded on the call's stream: main = the fused enumeration/contraction kernel, total =
  * first to last kernel. */
 int fp4_last_timing(const fp4_ctx *ctx, double *ms_main, double *ms_total);
+
+/* ---------------------------------------------------------------- batched instances
+ * Several crystals (uneven branch counts, grids, quartet lists) evaluated by one captured HIP
+ * graph: per instance occupations and precontraction, one persistent kernel per branch-count
+ * class whose work-groups take (instance, target, q'-chunk) items from a global atomic
+ * counter until it passes the total, per instance ordered reduction.  The graph is captured
+ * on the first call and replayed while the instance buffers are unchanged; temperatures are
+ * read from device memory at replay time. */
+
+/* Create an empty batch on HIP device `device_id`. */
+int fp4_batch_create(fp4_batch **out, int device_id);
+
+/* Release the batch (not the contexts added to it). */
+void fp4_batch_destroy(fp4_batch *b);
+
+/* Add a fully loaded context (same device).  The caller keeps the context alive while the
+ * batch is used; at most 64 instances. */
+int fp4_batch_add(fp4_batch *b, fp4_ctx *ctx);
+
+/* Rates of every mode of every instance.
+ *   T[nT], 1 <= nT <= 4; scalebroad, mask, precision as in fp4_compute_rates4
+ *   rates   host, concatenated in the order of fp4_batch_add: for instance i a block
+ *           [nT][nq_i*nb_i] (1/ps)
+ *   counts  host, concatenated blocks [nq_i*nb_i][3], or NULL
+ * Each instance uses its context's q'-chunk (FP4_PARAM_QCHUNK or fp4_autotune), 16 if
+ * unset.  Synchronous. */
+int fp4_batch_compute(fp4_batch *b, const double *T, int32_t nT, double scalebroad,
+                      uint32_t mask, int32_t precision, double *rates, int64_t *counts);
+
+/* Device time (ms) of the last graph launch, and how many graphs were captured and
+ * launched so far. */
+int fp4_batch_last_timing(const fp4_batch *b, double *ms_graph, int64_t *graph_builds,
+                          int64_t *graph_launches);
+
+/* Reason of the last batch error. */
+const char *fp4_batch_last_error(const fp4_batch *b);
+
+/* Autotuner: times the persistent pipeline on `nsample` evenly spaced active modes of the
+ * context for q'-chunk sizes 1, 2, 4, ..., 128 and N (those below N), keeps the fastest as
+ * the context's FP4_PARAM_QCHUNK and returns it in *best_qchunk.  ms_out / qchunk_out
+ * (nullable, ncand_max entries) receive the measured times and the candidates; *ncand the
+ * number of candidates.  1 <= nT <= 4. */
+int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, uint32_t mask,
+                 int32_t precision, int32_t nsample, int32_t *best_qchunk, double *ms_out,
+                 int32_t *qchunk_out, int32_t ncand_max, int32_t *ncand);
 
 /* Human-readable reason of the last error on this context ("" if none). */
 const char *fp4_last_error(const fp4_ctx *ctx);

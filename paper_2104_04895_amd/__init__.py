@@ -36,7 +36,9 @@ EXPORTED = [
     "fp4_create", "fp4_destroy", "fp4_load_lattice", "fp4_load_modes", "fp4_load_fc4",
     "fp4_set_param", "fp4_compute_rates4", "fp4_compute_rates4_subset",
     "fp4_compute_rates4_async", "fp4_debug_matrix_elements", "fp4_last_stats",
-    "fp4_last_timing", "fp4_last_error", "fp4_strerror",
+    "fp4_last_timing", "fp4_last_error", "fp4_strerror", "fp4_batch_create",
+    "fp4_batch_destroy", "fp4_batch_add", "fp4_batch_compute", "fp4_batch_last_timing",
+    "fp4_batch_last_error", "fp4_autotune",
 ]
 
 _lib = None
@@ -74,6 +76,15 @@ def lib():
         L.fp4_last_error.restype = ctypes.c_char_p
         L.fp4_strerror.argtypes = [ctypes.c_int]
         L.fp4_strerror.restype = ctypes.c_char_p
+        L.fp4_batch_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        L.fp4_batch_destroy.argtypes = [P]
+        L.fp4_batch_destroy.restype = None
+        L.fp4_batch_add.argtypes = [P, P]
+        L.fp4_batch_compute.argtypes = [P, P, i32, f64, u32, i32, P, P]
+        L.fp4_batch_last_timing.argtypes = [P, P, P, P]
+        L.fp4_batch_last_error.argtypes = [P]
+        L.fp4_batch_last_error.restype = ctypes.c_char_p
+        L.fp4_autotune.argtypes = [P, P, i32, f64, u32, i32, i32, P, P, P, i32, P]
         _lib = L
     return _lib
 
@@ -203,6 +214,81 @@ class Context:
         a, b = ctypes.c_double(), ctypes.c_double()
         self._check(self._L.fp4_last_timing(self._h, ctypes.byref(a), ctypes.byref(b)), "fp4_last_timing")
         return {"ms_main": a.value, "ms_total": b.value}
+
+
+class Batch:
+    """Several loaded Contexts evaluated by one captured HIP graph (fp4_batch_*)."""
+
+    def __init__(self, device: int = 0):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        rc = self._L.fp4_batch_create(ctypes.byref(h), int(device))
+        if rc != FP4_OK:
+            raise Fp4Error(rc, "fp4_batch_create failed")
+        self._h = h
+        self.ctxs = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fp4_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != FP4_OK:
+            raise Fp4Error(rc, f"{what}: {self._L.fp4_batch_last_error(self._h).decode()}")
+
+    def add(self, ctx: "Context"):
+        self._check(self._L.fp4_batch_add(self._h, ctx._h), "fp4_batch_add")
+        self.ctxs.append(ctx)
+
+    def compute(self, T, scalebroad=1.0, mask=7, precision=FP4_FP64):
+        """Returns ([rates_i [nT][nmodes_i]], [counts_i [nmodes_i][3]])."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        sizes = [c.nq * c.nb for c in self.ctxs]
+        rates = np.zeros(len(T) * sum(sizes))
+        counts = np.zeros(3 * sum(sizes), dtype=np.int64)
+        self._check(self._L.fp4_batch_compute(self._h, _p(T), len(T), float(scalebroad), int(mask),
+                                              int(precision), _p(rates), _p(counts)),
+                    "fp4_batch_compute")
+        out_r, out_c, o_r, o_c = [], [], 0, 0
+        for n in sizes:
+            out_r.append(rates[o_r:o_r + len(T) * n].reshape(len(T), n))
+            out_c.append(counts[o_c:o_c + 3 * n].reshape(n, 3))
+            o_r += len(T) * n
+            o_c += 3 * n
+        return out_r, out_c
+
+    def last_timing(self):
+        ms, nb_, nl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._L.fp4_batch_last_timing(self._h, ctypes.byref(ms), ctypes.byref(nb_),
+                                                  ctypes.byref(nl)), "fp4_batch_last_timing")
+        return {"ms_graph": ms.value, "graph_builds": nb_.value, "graph_launches": nl.value}
+
+
+def autotune(ctx: "Context", T, scalebroad=1.0, mask=7, precision=FP4_FP64, nsample=64):
+    """Run the q'-chunk autotuner on a context; returns (best, {qchunk: ms})."""
+    L = lib()
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    best = ctypes.c_int32()
+    ms = np.zeros(16)
+    qs = np.zeros(16, dtype=np.int32)
+    n = ctypes.c_int32()
+    ctx._check(L.fp4_autotune(ctx._h, _p(T), len(T), float(scalebroad), int(mask), int(precision),
+                              int(nsample), ctypes.byref(best), _p(ms), _p(qs), 16, ctypes.byref(n)),
+               "fp4_autotune")
+    return best.value, {int(qs[i]): float(ms[i]) for i in range(n.value)}
 
 
 def build():

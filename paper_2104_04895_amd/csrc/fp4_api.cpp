@@ -789,3 +789,377 @@ int fp4_last_timing(const fp4_ctx *ctx, double *ms_main, double *ms_total) {
 }
 
 }  // extern "C"
+
+// ====================================================================== batched instances
+
+struct fp4_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<fp4_ctx *> ctxs;
+  std::string err;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string key;
+  DevBuf d_inst[4];       // instance tables of the branch-count classes nb = 3, 6, 9, 12
+  DevBuf d_counter;       // one work counter per class
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double ms_last = 0.0;
+  long long graph_builds = 0, graph_launches = 0;
+  int fail(int code, const std::string &msg) {
+    err = msg;
+    return code;
+  }
+};
+
+namespace {
+
+// Eager preparation of one crystal for the persistent kernel: tables, temperatures, target
+// list, buffers; fills the instance descriptor (no kernel is enqueued here).
+int prepare_instance(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask,
+                     int precision, const std::vector<int> &targets, int qchunk,
+                     fp4::BatchInst *out) {
+  int rc;
+  const int fp32 = precision == FP4_FP32;
+  const size_t nmodes = (size_t)ctx->N * ctx->nb;
+  const int nt = (int)targets.size();
+  if ((rc = ensure_tables(ctx))) return rc;
+  if ((rc = upload(ctx, ctx->d_T, T, (size_t)nT))) return rc;
+  if ((rc = upload(ctx, ctx->d_targets, targets.data(), targets.size()))) return rc;
+  FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if ((rc = ensure(ctx, ctx->d_occ, nmodes * nT * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_iocc, nmodes * nT * sizeof(double)))) return rc;
+  if (qchunk < 1) qchunk = 1;
+  if (qchunk > ctx->N) qchunk = ctx->N;
+  const int nchunk = (ctx->N + qchunk - 1) / qchunk;
+  const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+  if ((rc = ensure(ctx, ctx->d_U, (size_t)nt * ctx->nc * 27 * cb))) return rc;
+  if ((rc = ensure(ctx, ctx->d_partial, (size_t)nt * nchunk * 3 * nT * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_pcount, (size_t)nt * nchunk * 3 * sizeof(unsigned long long)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_blocks, sizeof(unsigned long long)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_rates, (size_t)nT * nt * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_counts, (size_t)nt * 3 * sizeof(long long)))) return rc;
+  fp4::RateArgs a{};
+  const double wsb = ctx->window_w * sb;
+  a.c_win = (wsb * ctx->dq) * (wsb * ctx->dq);
+  a.sqrt_c_win = wsb * ctx->dq;
+  a.c_sig = (sb * ctx->dq) * (sb * ctx->dq);
+  a.c_min = ctx->sigma_min * ctx->sigma_min;
+  a.kpref = c4_prefactor() / ((double)ctx->N * (double)ctx->N);
+  a.nT = nT;
+  a.mask = mask;
+  a.occ = (const double *)ctx->d_occ.p;
+  a.inv_occ = (const double *)ctx->d_iocc.p;
+  a.targets = (const int *)ctx->d_targets.p;
+  a.nt = nt;
+  a.t0 = 0;
+  a.qchunk = qchunk;
+  a.nchunk = nchunk;
+  a.U = ctx->d_U.p;
+  a.partial = (double *)ctx->d_partial.p;
+  a.pcount = (unsigned long long *)ctx->d_pcount.p;
+  a.blocks = (unsigned long long *)ctx->d_blocks.p;
+  out->c = make_crystal(ctx);
+  out->a = a;
+  out->item0 = 0;
+  return FP4_OK;
+}
+
+int nb_class(int nb) { return nb / 3 - 1; }
+
+// estimated relative cost of one item (one target, one q'-chunk): blocks x block cost
+double item_cost(const fp4::BatchInst &b) {
+  const double nb = b.c.nb;
+  return (double)b.a.qchunk * nb * b.c.N * (9.0 * b.c.ng + 2.0 * nb * nb * nb);
+}
+
+// Enqueue the whole batched computation on stream s: per instance occupations and
+// precontraction, counter reset, one persistent kernel per branch-count class, per
+// instance ordered reduction.  Also used inside stream capture.
+int enqueue_batch(fp4_batch *b, std::vector<fp4::BatchInst> (&cls)[4], int fp32, int nT,
+                  const std::vector<fp4_ctx *> &ctxs, const std::vector<fp4::BatchInst> &insts,
+                  hipStream_t s) {
+  for (size_t i = 0; i < ctxs.size(); ++i) {
+    fp4_ctx *ctx = ctxs[i];
+    const fp4::BatchInst &bi = insts[i];
+    FP4_HIP(b, fp4::launch_occupations(bi.c, (const double *)ctx->d_T.p, nT, hbar_over_kb_kps(),
+                                       (double *)ctx->d_occ.p, (double *)ctx->d_iocc.p, s));
+    FP4_HIP(b, fp4::launch_precontract(bi.c, bi.a.targets, bi.a.nt, fp32, ctx->d_U.p, s));
+    FP4_HIP(b, fp4::launch_zero(ctx->d_blocks.p, sizeof(unsigned long long), s));
+  }
+  FP4_HIP(b, fp4::launch_zero(b->d_counter.p, 4 * sizeof(unsigned long long), s));
+  for (int k = 0; k < 4; ++k) {
+    if (cls[k].empty()) continue;
+    long long total = 0;
+    size_t lds = 0;
+    for (auto &bi : cls[k]) {
+      total = std::max(total, bi.item0 + (long long)bi.a.nt * bi.a.nchunk);
+      lds = std::max(lds, fp4::batch_lds_bytes(bi.c, fp32, nT));
+    }
+    hipError_t e = fp4::launch_batch((const fp4::BatchInst *)b->d_inst[k].p, (int)cls[k].size(), total,
+                                     (unsigned long long *)b->d_counter.p + k, lds, fp32,
+                                     3 * (k + 1), nT, nullptr, s);
+    if (e == hipErrorInvalidValue)
+      return b->fail(FP4_E_UNSUPPORTED, "an instance needs more LDS than a work-group has");
+    FP4_HIP(b, e);
+  }
+  for (size_t i = 0; i < ctxs.size(); ++i) {
+    fp4_ctx *ctx = ctxs[i];
+    const fp4::BatchInst &bi = insts[i];
+    FP4_HIP(b, fp4::launch_reduce(bi.a, bi.a.nt, (double *)ctx->d_rates.p, nullptr,
+                                  (long long *)ctx->d_counts.p, s));
+  }
+  return FP4_OK;
+}
+
+// Prepare every instance, order the items of each class by cost per item, upload the
+// instance tables.
+int build_classes(fp4_batch *b, const std::vector<fp4_ctx *> &ctxs,
+                  const std::vector<std::vector<int>> &targets, const double *T, int nT,
+                  double sb, uint32_t mask, int precision, const std::vector<int> &qchunks,
+                  std::vector<fp4::BatchInst> &insts, std::vector<fp4::BatchInst> (&cls)[4]) {
+  insts.assign(ctxs.size(), fp4::BatchInst{});
+  for (int k = 0; k < 4; ++k) cls[k].clear();
+  for (size_t i = 0; i < ctxs.size(); ++i) {
+    int rc = prepare_instance(ctxs[i], T, nT, sb, mask, precision, targets[i], qchunks[i], &insts[i]);
+    if (rc) return b->fail(rc, std::string("instance ") + std::to_string(i) + ": " + ctxs[i]->err);
+  }
+  std::vector<size_t> order(ctxs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return item_cost(insts[x]) > item_cost(insts[y]); });
+  for (size_t o : order) {
+    const int k = nb_class(insts[o].c.nb);
+    long long item0 = 0;
+    if (!cls[k].empty()) item0 = cls[k].back().item0 + (long long)cls[k].back().a.nt * cls[k].back().a.nchunk;
+    insts[o].item0 = item0;
+    cls[k].push_back(insts[o]);
+  }
+  int rc;
+  if ((rc = ensure(ctxs[0], b->d_counter, 4 * sizeof(unsigned long long)))) return b->fail(rc, ctxs[0]->err);
+  for (int k = 0; k < 4; ++k) {
+    if (cls[k].empty()) continue;
+    if ((rc = ensure(ctxs[0], b->d_inst[k], cls[k].size() * sizeof(fp4::BatchInst)))) return b->fail(rc, ctxs[0]->err);
+    FP4_HIP(b, hipMemcpy(b->d_inst[k].p, cls[k].data(), cls[k].size() * sizeof(fp4::BatchInst), hipMemcpyHostToDevice));
+  }
+  return FP4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fp4_batch_create(fp4_batch **out, int device_id) {
+  if (!out) return FP4_E_INVAL;
+  *out = nullptr;
+  fp4_batch *b = new (std::nothrow) fp4_batch();
+  if (!b) return FP4_E_NOMEM;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device_id < 0 || device_id >= ndev ||
+      hipSetDevice(device_id) != hipSuccess || hipStreamCreate(&b->stream) != hipSuccess ||
+      hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return FP4_E_DEVICE;
+  }
+  b->device = device_id;
+  *out = b;
+  return FP4_OK;
+}
+
+void fp4_batch_destroy(fp4_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto &d : b->d_inst) release(d);
+  release(b->d_counter);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+const char *fp4_batch_last_error(const fp4_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int fp4_batch_add(fp4_batch *b, fp4_ctx *ctx) {
+  if (!b) return FP4_E_INVAL;
+  if (!ctx) return b->fail(FP4_E_INVAL, "null context");
+  if (ctx->device != b->device) return b->fail(FP4_E_INVAL, "context is on another device");
+  if (!ctx->have_lattice || !ctx->have_modes || !ctx->have_fc4)
+    return b->fail(FP4_E_STATE, "context is not fully loaded");
+  if (b->ctxs.size() >= 64) return b->fail(FP4_E_UNSUPPORTED, "at most 64 instances per batch");
+  for (fp4_ctx *c : b->ctxs)
+    if (c == ctx) return b->fail(FP4_E_INVAL, "context already in the batch");
+  b->ctxs.push_back(ctx);
+  b->key.clear();
+  return FP4_OK;
+}
+
+int fp4_batch_compute(fp4_batch *b, const double *T, int32_t nT, double scalebroad, uint32_t mask,
+                      int32_t precision, double *rates, int64_t *counts) {
+  if (!b) return FP4_E_INVAL;
+  try {
+    if (b->ctxs.empty()) return b->fail(FP4_E_STATE, "empty batch");
+    if (!rates) return b->fail(FP4_E_INVAL, "rates output is required");
+    if (nT > 4) return b->fail(FP4_E_UNSUPPORTED, "a batch takes at most 4 temperatures");
+    for (fp4_ctx *ctx : b->ctxs) {
+      const int rc = check_compute_args(ctx, T, nT, scalebroad, mask, precision);
+      if (rc) return b->fail(rc, ctx->err);
+    }
+    (void)hipSetDevice(b->device);
+    const int fp32 = precision == FP4_FP32;
+    std::vector<std::vector<int>> targets(b->ctxs.size());
+    std::vector<int> qchunks(b->ctxs.size());
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+      const int nm = b->ctxs[i]->N * b->ctxs[i]->nb;
+      targets[i].resize(nm);
+      for (int m = 0; m < nm; ++m) targets[i][m] = m;
+      qchunks[i] = b->ctxs[i]->qchunk > 0 ? b->ctxs[i]->qchunk : 16;
+    }
+    std::vector<fp4::BatchInst> insts;
+    std::vector<fp4::BatchInst> cls[4];
+    int rc = build_classes(b, b->ctxs, targets, T, nT, scalebroad, mask, precision, qchunks, insts, cls);
+    if (rc) return rc;
+    // graph signature: every device pointer and size the captured work uses
+    std::string key = std::to_string(nT) + "/" + std::to_string(fp32);
+    for (int k = 0; k < 4; ++k)
+      for (auto &bi : cls[k]) {
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(&bi);
+        key.append(reinterpret_cast<const char *>(p), sizeof(bi));
+      }
+    for (fp4_ctx *ctx : b->ctxs) {
+      const void *ps[] = {ctx->d_T.p, ctx->d_U.p, ctx->d_rates.p, ctx->d_counts.p, ctx->d_blocks.p};
+      key.append(reinterpret_cast<const char *>(ps), sizeof(ps));
+    }
+    if (key != b->key || !b->exec) {
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+      FP4_HIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+      rc = enqueue_batch(b, cls, fp32, nT, b->ctxs, insts, b->stream);
+      hipGraph_t g = nullptr;
+      const hipError_t ee = hipStreamEndCapture(b->stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      FP4_HIP(b, ee);
+      b->graph = g;
+      FP4_HIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->key = key;
+      b->graph_builds++;
+    }
+    FP4_HIP(b, hipEventRecord(b->ev0, b->stream));
+    FP4_HIP(b, hipGraphLaunch(b->exec, b->stream));
+    FP4_HIP(b, hipEventRecord(b->ev1, b->stream));
+    b->graph_launches++;
+    size_t off_r = 0, off_c = 0;
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+      fp4_ctx *ctx = b->ctxs[i];
+      const size_t nm = (size_t)ctx->N * ctx->nb;
+      // rates of instance i: [nT][nm] at offset sum of nT*nm of the previous instances
+      FP4_HIP(b, hipMemcpyAsync(rates + off_r, ctx->d_rates.p, (size_t)nT * nm * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+      if (counts)
+        FP4_HIP(b, hipMemcpyAsync(counts + off_c, ctx->d_counts.p, nm * 3 * sizeof(long long), hipMemcpyDeviceToHost, b->stream));
+      off_r += (size_t)nT * nm;
+      off_c += nm * 3;
+    }
+    FP4_HIP(b, hipStreamSynchronize(b->stream));
+    float ms = 0.f;
+    FP4_HIP(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    b->ms_last = ms;
+    b->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return b->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_batch_last_timing(const fp4_batch *b, double *ms_graph, int64_t *graph_builds,
+                          int64_t *graph_launches) {
+  if (!b) return FP4_E_INVAL;
+  if (ms_graph) *ms_graph = b->ms_last;
+  if (graph_builds) *graph_builds = b->graph_builds;
+  if (graph_launches) *graph_launches = b->graph_launches;
+  return FP4_OK;
+}
+
+int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, uint32_t mask,
+                 int32_t precision, int32_t nsample, int32_t *best_qchunk, double *ms_out,
+                 int32_t *qchunk_out, int32_t ncand_max, int32_t *ncand) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    int rc = check_compute_args(ctx, T, nT, scalebroad, mask, precision);
+    if (rc) return rc;
+    if (nT > 4) return ctx->fail(FP4_E_UNSUPPORTED, "autotuning takes at most 4 temperatures");
+    if (nsample < 1) return ctx->fail(FP4_E_INVAL, "nsample must be >= 1");
+    (void)hipSetDevice(ctx->device);
+    // sample: evenly spaced active modes
+    const int nm = ctx->N * ctx->nb;
+    std::vector<double> om(nm);
+    FP4_HIP(ctx, hipMemcpy(om.data(), ctx->d_omega.p, nm * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<int> act;
+    for (int m = 0; m < nm; ++m)
+      if (om[m] > 0.0) act.push_back(m);
+    if (act.empty()) return ctx->fail(FP4_E_STATE, "no active mode");
+    std::vector<int> sample;
+    const int ns = std::min<int>(nsample, (int)act.size());
+    for (int i = 0; i < ns; ++i) sample.push_back(act[(size_t)i * act.size() / ns]);
+    std::vector<int> cand;
+    for (int q : {1, 2, 4, 8, 16, 32, 64, 128})
+      if (q < ctx->N) cand.push_back(q);
+    cand.push_back(ctx->N);
+    fp4_batch *b = nullptr;
+    if ((rc = fp4_batch_create(&b, ctx->device))) return ctx->fail(rc, "batch context creation failed");
+    double best_ms = 1e300;
+    int best = cand[0];
+    std::vector<double> times;
+    for (size_t ci = 0; ci <= cand.size(); ++ci) {
+      // the first pass (ci == 0, repeated) warms caches and code; it is not counted
+      const int q = cand[ci == 0 ? 0 : ci - 1];
+      std::vector<fp4::BatchInst> insts;
+      std::vector<fp4::BatchInst> cls[4];
+      std::vector<fp4_ctx *> one{ctx};
+      rc = build_classes(b, one, {sample}, T, nT, scalebroad, mask, precision, {q}, insts, cls);
+      if (!rc) {
+        rc = enqueue_batch(b, cls, precision == FP4_FP32, nT, one, insts, b->stream);
+        if (!rc && hipEventRecord(b->ev0, b->stream) != hipSuccess) rc = FP4_E_DEVICE;
+      }
+      // time only the persistent part: re-enqueue after the first event
+      if (!rc) {
+        rc = enqueue_batch(b, cls, precision == FP4_FP32, nT, one, insts, b->stream);
+        if (!rc && (hipEventRecord(b->ev1, b->stream) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)) rc = FP4_E_DEVICE;
+      }
+      if (rc) {
+        const std::string msg = b->err;
+        fp4_batch_destroy(b);
+        return ctx->fail(rc, "autotune: " + msg);
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+      if (ci == 0) continue;
+      times.push_back(ms);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = q;
+      }
+    }
+    fp4_batch_destroy(b);
+    ctx->qchunk = best;
+    if (best_qchunk) *best_qchunk = best;
+    if (ncand) *ncand = (int)times.size();
+    for (int i = 0; i < (int)times.size() && i < ncand_max; ++i) {
+      if (ms_out) ms_out[i] = times[i];
+      if (qchunk_out) qchunk_out[i] = cand[i];
+    }
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+}  // extern "C"

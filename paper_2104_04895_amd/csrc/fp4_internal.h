@@ -65,6 +65,13 @@ struct RateArgs {
   unsigned long long *blocks; // [1] contracted branch blocks (atomic)
 };
 
+// One crystal of a persistent batched launch; items item0 .. item0 + nt*nchunk - 1.
+struct BatchInst {
+  Crystal c;
+  RateArgs a;
+  long long item0;
+};
+
 // launchers (fp4_kernels.hip)
 hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
@@ -80,5 +87,9 @@ hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double 
 hipError_t launch_debug_v(const Crystal &c, const int *quads, int n, const int *tslot,
                           const void *U, int fp32, double2 *V, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+size_t batch_lds_bytes(const Crystal &c, int fp32, int nT);
+hipError_t launch_batch(const BatchInst *insts, int ninst, long long total,
+                        unsigned long long *counter, size_t lds, int fp32, int nb, int nT,
+                        int *grid_out, hipStream_t s);
 
 }  // namespace fp4

@@ -516,12 +516,15 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   }
 }
 
+// The work of one (target t of the batch, q'-chunk) item: every lambda' of the chunk, all
+// channels, partial rates and counts written to the item's slot.  Called by the whole
+// work-group (it synchronises internally).
 template <typename R, int NB, int NT>
-__global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
+__device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, int t, int chunk,
+                                          unsigned char *smem) {
   using CR = typename CT<R>::T;
   constexpr int GPW = 64 / NB;
   constexpr int NGRP = 4 * GPW;
-  extern __shared__ __align__(16) unsigned char smem[];
   CR *W = reinterpret_cast<CR *>(smem);                 // [2][ng][9]
   CR *X = W + 2 * c.ng * 9;                             // [NGRP][NB][NB]
   CR *P = X + NGRP * NB * NB;                           // [NGRP][nd]
@@ -539,7 +542,6 @@ __global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
   for (int i = tid; i < c.ng; i += 256) sg_d[i] = c.g_d[i];
   for (int i = tid; i <= c.nat * c.nat; i += 256) skl[i] = c.kl_start[i];
 
-  const int t = blockIdx.x / a.nchunk, chunk = blockIdx.x - t * a.nchunk;
   const int mu = a.targets[t];
   const int iq = mu / NB;
   Acc<NT> acc;
@@ -621,6 +623,45 @@ __global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
   }
 }
 
+template <typename R, int NB, int NT>
+__global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int t = blockIdx.x / a.nchunk, chunk = blockIdx.x - t * a.nchunk;
+  rate_body<R, NB, NT>(c, a, t, chunk, smem);
+}
+
+// Persistent form over several crystals with the same branch count (uneven grids, quartet
+// lists and mode counts): every work-group takes (instance, target, q'-chunk) items from one
+// global atomic counter until the counter passes the total; items are numbered instance by
+// instance (the host orders the instances by cost per item, most expensive first).  Crystals
+// of different branch counts run as separate persistent kernels of the same graph.
+template <typename R, int NB, int NT>
+__global__ __launch_bounds__(256, 2) void k_rates_batch(const BatchInst *__restrict__ insts, int ninst,
+                                                        long long total,
+                                                        unsigned long long *counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ long long item_s;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    // the item and the instance index are wave-uniform: keep them (and so the instance
+    // descriptor loads) in scalar registers
+    const long long iv = item_s;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(iv & 0xffffffffll));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)iv >> 32));
+    const long long item = (long long)(((unsigned long long)hi << 32) | lo);
+    if (item >= total) break;
+    int i = 0;
+    while (i + 1 < ninst && item >= insts[i + 1].item0) ++i;
+    i = __builtin_amdgcn_readfirstlane(i);
+    const long long local = item - insts[i].item0;
+    const int nchunk = insts[i].a.nchunk;
+    const int t = (int)(local / nchunk), chunk = (int)(local - (long long)t * nchunk);
+    rate_body<R, NB, NT>(insts[i].c, insts[i].a, t, chunk, smem);
+  }
+}
+
 // ordered reduction over q'-chunks: rates[T][t], per channel, counts
 __global__ void k_reduce(const double *partial, const unsigned long long *pcount, int nt,
                          int nchunk, int nT, double *rates, double *rates_ch,
@@ -688,15 +729,18 @@ __global__ void k_zero(unsigned long long *p, size_t n) {
   if (i < n) p[i] = 0ull;
 }
 
-template <typename R, int NB, int NT>
-hipError_t launch_rates_t(const Crystal &c, const RateArgs &a, hipStream_t s) {
-  using CR = typename CT<R>::T;
-  constexpr int GPW = 64 / NB;
-  const size_t lds = sizeof(CR) * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB +
-                                   (size_t)4 * GPW * c.nd) +
+size_t rate_lds_bytes(const Crystal &c, int fp32, int NT) {
+  const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+  const int NB = c.nb, GPW = 64 / NB;
+  const size_t lds = cb * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB + (size_t)4 * GPW * c.nd) +
                      sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1 + 4 * QSEG);
   const size_t lds_red = sizeof(double) * 4 * 3 * NT + sizeof(unsigned long long) * 16;
-  const size_t bytes = lds > lds_red ? lds : lds_red;
+  return lds > lds_red ? lds : lds_red;
+}
+
+template <typename R, int NB, int NT>
+hipError_t launch_rates_t(const Crystal &c, const RateArgs &a, hipStream_t s) {
+  const size_t bytes = rate_lds_bytes(c, sizeof(R) == 4, NT);
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((size_t)a.nt * a.nchunk);
   hipLaunchKernelGGL((k_rates<R, NB, NT>), dim3(grid), dim3(256), bytes, s, c, a);
@@ -783,6 +827,59 @@ hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream
   return fp32 ? launch_rates_r<float>(c, a, s) : launch_rates_r<double>(c, a, s);
 }
 
+size_t batch_lds_bytes(const Crystal &c, int fp32, int nT) {
+  return rate_lds_bytes(c, fp32, nT <= 1 ? 1 : nT <= 2 ? 2 : 4) + 64;
+}
+
+template <typename R, int NB, int NT>
+hipError_t launch_batch_t(const BatchInst *insts, int ninst, long long total,
+                          unsigned long long *counter, size_t lds, int *grid_out, hipStream_t s) {
+  if (lds > 160 * 1024 - 64) return hipErrorInvalidValue;
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rates_batch<R, NB, NT>, 256, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  long long grid = (long long)ncu * per_cu;
+  if (grid > total) grid = total;
+  if (grid < 1) grid = 1;
+  if (grid_out) *grid_out = (int)grid;
+  hipLaunchKernelGGL((k_rates_batch<R, NB, NT>), dim3((unsigned)grid), dim3(256), lds, s, insts,
+                     ninst, total, counter);
+  return hipGetLastError();
+}
+
+template <typename R, int NB>
+hipError_t launch_batch_nb(const BatchInst *insts, int ninst, long long total,
+                           unsigned long long *counter, size_t lds, int nT, int *grid_out,
+                           hipStream_t s) {
+  if (nT <= 1) return launch_batch_t<R, NB, 1>(insts, ninst, total, counter, lds, grid_out, s);
+  if (nT <= 2) return launch_batch_t<R, NB, 2>(insts, ninst, total, counter, lds, grid_out, s);
+  return launch_batch_t<R, NB, 4>(insts, ninst, total, counter, lds, grid_out, s);
+}
+
+template <typename R>
+hipError_t launch_batch_r(const BatchInst *insts, int ninst, long long total,
+                          unsigned long long *counter, size_t lds, int nb, int nT,
+                          int *grid_out, hipStream_t s) {
+  switch (nb) {
+    case 3: return launch_batch_nb<R, 3>(insts, ninst, total, counter, lds, nT, grid_out, s);
+    case 6: return launch_batch_nb<R, 6>(insts, ninst, total, counter, lds, nT, grid_out, s);
+    case 9: return launch_batch_nb<R, 9>(insts, ninst, total, counter, lds, nT, grid_out, s);
+    case 12: return launch_batch_nb<R, 12>(insts, ninst, total, counter, lds, nT, grid_out, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch(const BatchInst *insts, int ninst, long long total,
+                        unsigned long long *counter, size_t lds, int fp32, int nb, int nT,
+                        int *grid_out, hipStream_t s) {
+  return fp32 ? launch_batch_r<float>(insts, ninst, total, counter, lds, nb, nT, grid_out, s)
+              : launch_batch_r<double>(insts, ninst, total, counter, lds, nb, nT, grid_out, s);
+}
 hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double *rates_ch,
                          long long *counts, hipStream_t s) {
   const int nthr = 128;
