@@ -65,6 +65,7 @@ extern "C" {
 
 typedef struct fp4_ctx fp4_ctx;
 typedef struct fp4_batch fp4_batch;
+typedef struct fp4_mlp fp4_mlp;
 
 /* Create a context on HIP device `device_id`.  *out receives the handle (NULL on error).
  * Returns FP4_E_DEVICE if the device cannot be used. */
@@ -200,6 +201,38 @@ const char *fp4_batch_last_error(const fp4_batch *b);
 int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, uint32_t mask,
                  int32_t precision, int32_t nsample, int32_t *best_qchunk, double *ms_out,
                  int32_t *qchunk_out, int32_t ncand_max, int32_t *ncand);
+
+/* ---------------------------------------------------------------- learned surrogate
+ * A small multilayer perceptron, trained and evaluated by the library's own kernels, that
+ * predicts a mode's log four-phonon rate (output 0) and the log standard deviation of that
+ * prediction (output 1) from per-mode features.  Layers nin -> width -> ... -> width -> 2
+ * (`depth` linear layers, SiLU between them); training minimises the Gaussian negative
+ * log-likelihood 0.5 (y - mu)^2 exp(-2 s) + s with Adam in FP32; inference runs in FP32 or
+ * with BF16 weights and activations (FP32 accumulation).  Parameters are one FP32 array:
+ * per layer W [out][in] then b [out]. */
+
+/* Create a network (2 <= depth <= 16, width <= 1024, nin <= 256), seeded initialisation. */
+int fp4_mlp_create(fp4_mlp **out, int device_id, int32_t nin, int32_t width, int32_t depth,
+                   uint64_t seed);
+void fp4_mlp_destroy(fp4_mlp *m);
+const char *fp4_mlp_last_error(const fp4_mlp *m);
+int64_t fp4_mlp_num_params(const fp4_mlp *m);
+int fp4_mlp_get_params(fp4_mlp *m, float *params);
+int fp4_mlp_set_params(fp4_mlp *m, const float *params);
+
+/* Mean loss over n samples (X [n][nin], y [n]) and its gradient with respect to every
+ * parameter (grad: nullable, num_params floats). */
+int fp4_mlp_loss_grad(fp4_mlp *m, const float *X, const float *y, int32_t n, double *loss,
+                      float *grad);
+
+/* `epochs` passes of Adam (lr, beta 0.9/0.999) over shuffled mini-batches of `batch` rows
+ * (the last incomplete batch of an epoch is skipped).  loss_per_epoch: nullable [epochs]. */
+int fp4_mlp_train(fp4_mlp *m, const float *X, const float *y, int32_t n, int32_t epochs,
+                  int32_t batch, float lr, uint64_t seed, double *loss_per_epoch);
+
+/* out [n][2] = (mu, s) for X [n][nin]; bf16 != 0 selects BF16 weights/activations.  *ms
+ * (nullable) receives the device time of the forward pass. */
+int fp4_mlp_predict(fp4_mlp *m, const float *X, int32_t n, int32_t bf16, float *out, double *ms);
 
 /* Human-readable reason of the last error on this context ("" if none). */
 const char *fp4_last_error(const fp4_ctx *ctx);

@@ -38,7 +38,9 @@ EXPORTED = [
     "fp4_compute_rates4_async", "fp4_debug_matrix_elements", "fp4_last_stats",
     "fp4_last_timing", "fp4_last_error", "fp4_strerror", "fp4_batch_create",
     "fp4_batch_destroy", "fp4_batch_add", "fp4_batch_compute", "fp4_batch_last_timing",
-    "fp4_batch_last_error", "fp4_autotune",
+    "fp4_batch_last_error", "fp4_autotune", "fp4_mlp_create", "fp4_mlp_destroy",
+    "fp4_mlp_last_error", "fp4_mlp_num_params", "fp4_mlp_get_params", "fp4_mlp_set_params",
+    "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict",
 ]
 
 _lib = None
@@ -85,6 +87,19 @@ def lib():
         L.fp4_batch_last_error.argtypes = [P]
         L.fp4_batch_last_error.restype = ctypes.c_char_p
         L.fp4_autotune.argtypes = [P, P, i32, f64, u32, i32, i32, P, P, P, i32, P]
+        u64 = ctypes.c_uint64
+        L.fp4_mlp_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, i32, i32, i32, u64]
+        L.fp4_mlp_destroy.argtypes = [P]
+        L.fp4_mlp_destroy.restype = None
+        L.fp4_mlp_last_error.argtypes = [P]
+        L.fp4_mlp_last_error.restype = ctypes.c_char_p
+        L.fp4_mlp_num_params.argtypes = [P]
+        L.fp4_mlp_num_params.restype = ctypes.c_int64
+        L.fp4_mlp_get_params.argtypes = [P, P]
+        L.fp4_mlp_set_params.argtypes = [P, P]
+        L.fp4_mlp_loss_grad.argtypes = [P, P, P, i32, P, P]
+        L.fp4_mlp_train.argtypes = [P, P, P, i32, i32, i32, ctypes.c_float, u64, P]
+        L.fp4_mlp_predict.argtypes = [P, P, i32, i32, P, P]
         _lib = L
     return _lib
 
@@ -275,6 +290,77 @@ class Batch:
         self._check(self._L.fp4_batch_last_timing(self._h, ctypes.byref(ms), ctypes.byref(nb_),
                                                   ctypes.byref(nl)), "fp4_batch_last_timing")
         return {"ms_graph": ms.value, "graph_builds": nb_.value, "graph_launches": nl.value}
+
+
+class Mlp:
+    """The surrogate network (fp4_mlp_*): FP32 training and FP32/BF16 inference on the GPU."""
+
+    def __init__(self, device: int = 0, nin: int = 10, width: int = 128, depth: int = 5,
+                 seed: int = 0):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        rc = self._L.fp4_mlp_create(ctypes.byref(h), int(device), int(nin), int(width), int(depth),
+                                    int(seed))
+        if rc != FP4_OK:
+            raise Fp4Error(rc, "fp4_mlp_create failed")
+        self._h = h
+        self.nin, self.width, self.depth = nin, width, depth
+        self.nparam = int(self._L.fp4_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fp4_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != FP4_OK:
+            raise Fp4Error(rc, f"{what}: {self._L.fp4_mlp_last_error(self._h).decode()}")
+
+    def get_params(self):
+        p = np.zeros(self.nparam, dtype=np.float32)
+        self._check(self._L.fp4_mlp_get_params(self._h, _p(p)), "fp4_mlp_get_params")
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self._L.fp4_mlp_set_params(self._h, _p(p)), "fp4_mlp_set_params")
+
+    def loss_grad(self, X, y):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        g = np.zeros(self.nparam, dtype=np.float32)
+        L = ctypes.c_double()
+        self._check(self._L.fp4_mlp_loss_grad(self._h, _p(X), _p(y), len(y), ctypes.byref(L), _p(g)),
+                    "fp4_mlp_loss_grad")
+        return L.value, g
+
+    def train(self, X, y, epochs=10, batch=256, lr=1e-3, seed=0):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        losses = np.zeros(epochs)
+        self._check(self._L.fp4_mlp_train(self._h, _p(X), _p(y), len(y), int(epochs), int(batch),
+                                          float(lr), int(seed), _p(losses)), "fp4_mlp_train")
+        return losses
+
+    def predict(self, X, bf16=True):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        out = np.zeros((len(X), 2), dtype=np.float32)
+        ms = ctypes.c_double()
+        self._check(self._L.fp4_mlp_predict(self._h, _p(X), len(X), 1 if bf16 else 0, _p(out),
+                                            ctypes.byref(ms)), "fp4_mlp_predict")
+        return out, ms.value
 
 
 def autotune(ctx: "Context", T, scalebroad=1.0, mask=7, precision=FP4_FP64, nsample=64):

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfp4.so")
-SOURCES = [os.path.join(HERE, "csrc", "fp4_api.cpp"), os.path.join(HERE, "csrc", "fp4_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "fp4_api.cpp"), os.path.join(HERE, "csrc", "fp4_kernels.hip"),
+           os.path.join(HERE, "csrc", "fp4_mlp.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
