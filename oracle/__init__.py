@@ -43,6 +43,13 @@ def lib():
         L.oracle_rates4_partners.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32,
                                              f64, f64, f64, i32, P, i32, P, i32, P, P, P, i32]
         L.oracle_rates4_partners.restype = ctypes.c_int
+        L.oracle_rates3.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, f64, f64, f64,
+                                    i32, P, P, P, i32]
+        L.oracle_rates3.restype = ctypes.c_int
+        L.oracle_v3.argtypes = [P, i32, P, P, P, P, i32, P, P, P, i32, P, P, P]
+        L.oracle_v3.restype = ctypes.c_int
+        L.oracle_c3.restype = f64
+        L.oracle_c3.argtypes = []
         L.oracle_v4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, i32, P, P, P]
         L.oracle_v4.restype = ctypes.c_int
         for name in ("oracle_hbar_over_kb", "oracle_c4"):
@@ -144,6 +151,47 @@ def v4(model: Model, modes4, signs4) -> np.ndarray:
     V = np.zeros(n, dtype=np.complex128)
     lib().oracle_v4(*model._common(), n, _p(modes4), _p(signs4), _p(V.view(np.float64)))
     return V
+
+
+def _fc3_args(model: Model, fc3):
+    at = np.ascontiguousarray(fc3.atoms, dtype=np.int32)
+    cl = np.ascontiguousarray(fc3.cells, dtype=np.int32)
+    ph = np.ascontiguousarray(fc3.phi, dtype=np.float64)
+    return [_p(model.grid), model.natoms, _p(model.mass), _p(model.omega), _p(model.evec),
+            _p(model.vel), int(at.shape[0]), _p(at), _p(cl), _p(ph)], (at, cl, ph)
+
+
+def rates3(model: Model, fc3, T, scalebroad, dq, targets=None, window_w=2.0, sigma_min=1e-4,
+           nthreads=0):
+    """Three-phonon rates (Eq. 3phgamma).  Returns (rates[nT][nt], counts[nt][2])."""
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    if targets is None:
+        targets = np.arange(model.nq * model.nb)
+    targets = np.ascontiguousarray(targets, dtype=np.int32)
+    nt = len(targets)
+    rates = np.zeros((len(T), nt))
+    counts = np.zeros((nt, 2), dtype=np.int64)
+    args, keep = _fc3_args(model, fc3)
+    rc = lib().oracle_rates3(*args, _p(T), len(T), float(scalebroad), float(window_w),
+                             float(sigma_min), float(dq), nt, _p(targets), _p(rates), _p(counts),
+                             int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_rates3 returned {rc}")
+    return rates, counts
+
+
+def v3(model: Model, fc3, modes3, signs3) -> np.ndarray:
+    """V of Eq. V3 for explicit (mode, sign) triples."""
+    modes3 = np.ascontiguousarray(modes3, dtype=np.int32).reshape(-1, 3)
+    signs3 = np.ascontiguousarray(signs3, dtype=np.int32).reshape(-1, 3)
+    V = np.zeros(len(modes3), dtype=np.complex128)
+    args, keep = _fc3_args(model, fc3)
+    lib().oracle_v3(*args, len(modes3), _p(modes3), _p(signs3), _p(V.view(np.float64)))
+    return V
+
+
+def c3() -> float:
+    return float(lib().oracle_c3())
 
 
 def c4() -> float:

@@ -471,3 +471,137 @@ double oracle_default_dq(const double A[9], const int32_t grid[3]) {
     const double N = (double)grid[0] * grid[1] * grid[2];
     return cbrt(detB / N);
 }
+
+/* ======================================================================= three-phonon
+ * Three-phonon RTA rate (Eq. tao0, 3ph bracket; Eq. 3phgamma; Eq. V3), used as an input
+ * feature of the learned surrogate:
+ *   1/tau_3ph(lambda) = (1/N) [ sum^{+} G^{+} + sum^{-} 1/2 G^{-} ]
+ *   G^{+} = hbar pi/4 (n' - n'') / (w w' w'') |V^{+}|^2 delta(w + w' - w''),  q'' = q + q'
+ *   G^{-} = hbar pi/4 (n' + n'' + 1) / (w w' w'') |V^{-}|^2 delta(w - w' - w''), q'' = q - q'
+ *   V^{+-} = sum_{ijk} sum_{abg} Phi e_a^{l}(i) e_b^{+-l'}(j) e_g^{-l''}(k) / sqrt(MMM)
+ *            exp(+-i q'.r_j) exp(-i q''.r_k)
+ * Readings (same as for four phonons): the adaptive Gaussian with sigma = sb |v' - v''| |dq|
+ * (derivative of the energy mismatch with respect to q' with q'' fixed by momentum), the
+ * window |dw| <= W sigma evaluated squared in the fixed order dw = (w +- w') - w'',
+ * s2 = (dx*dx + dy*dy) + dz*dz with d = v' - v'', delta := 1 below sigma_min, inactive modes
+ * excluded.  Triplets: atoms[n][3], cells[n][2][3] (atoms j, k; atom i in the home cell),
+ * phi[n][27] eV/A^3 with index (a*3+b)*3+g. */
+
+/* hbar pi / 4 for V in eV/(A^3 amu^1.5), delta in ps, omega in rad/ps, rate in 1/ps */
+double oracle_c3(void) {
+    const double kv = EV / (ANG * ANG * ANG * AMU * sqrt(AMU));
+    return HBAR * M_PI / 4.0 * kv * kv * 1.0e-60;
+}
+
+static cplx v3_general(const model_t *m, int n3, const int32_t *atoms, const int32_t *cells,
+                       const double *phi, const int mode[3], const int sg[3]) {
+    cplx V = 0.0;
+    for (int n = 0; n < n3; ++n) {
+        const int32_t *at = atoms + 3 * n;
+        cplx X[3][3];
+        for (int s = 0; s < 3; ++s) {
+            const int32_t *R = s == 0 ? ZERO_CELL : cells + 6 * n + 3 * (s - 1);
+            const int iq = mode[s] / m->nb, j = mode[s] % m->nb;
+            for (int x = 0; x < 3; ++x) X[s][x] = slot_factor(m, sg[s], iq, j, at[s], R, x);
+        }
+        const double *ph = phi + 27 * (size_t)n;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int c = 0; c < 3; ++c) V += ph[(a * 3 + b) * 3 + c] * X[0][a] * X[1][b] * X[2][c];
+    }
+    return V;
+}
+
+/* Public: V of Eq. V3 for explicit (mode, sign) triples. */
+int oracle_v3(const int32_t grid[3], int32_t natoms, const double *mass, const double *omega,
+              const double *evec, const double *vel, int32_t n3, const int32_t *atoms,
+              const int32_t *cells, const double *phi, int32_t n, const int32_t *modes3,
+              const int32_t *signs3, double *V) {
+    model_t m;
+    model_init(&m, grid, natoms, mass, omega, evec, vel, 0, NULL, NULL, NULL);
+    for (int i = 0; i < n; ++i) {
+        int md[3], sg[3];
+        for (int s = 0; s < 3; ++s) { md[s] = modes3[3 * i + s]; sg[s] = signs3[3 * i + s]; }
+        const cplx v = v3_general(&m, n3, atoms, cells, phi, md, sg);
+        V[2 * i] = creal(v); V[2 * i + 1] = cimag(v);
+    }
+    model_free(&m);
+    return 0;
+}
+
+/* Public: three-phonon rates rates[nT][ntargets] and kept counts counts[ntargets][2]
+ * (channel +, channel -). */
+int oracle_rates3(const int32_t grid[3], int32_t natoms, const double *mass,
+                  const double *omega, const double *evec, const double *vel, int32_t n3,
+                  const int32_t *atoms, const int32_t *cells, const double *phi,
+                  const double *T, int32_t nT, double scalebroad, double window_w,
+                  double sigma_min, double dq, int32_t ntargets, const int32_t *targets,
+                  double *rates, int64_t *counts, int32_t nthreads) {
+    if (natoms <= 0 || nT <= 0 || ntargets < 0 || scalebroad <= 0.0 || dq <= 0.0) return -1;
+    model_t m;
+    model_init(&m, grid, natoms, mass, omega, evec, vel, 0, NULL, NULL, NULL);
+    const int N = m.N, nb = m.nb, nmodes = N * nb;
+    const double c_win = ((window_w * scalebroad) * dq) * ((window_w * scalebroad) * dq);
+    const double c_sig = (scalebroad * dq) * (scalebroad * dq);
+    const double C3 = oracle_c3();
+    const double hk = oracle_hbar_over_kb();
+    double *occ = (double *)calloc((size_t)nT * nmodes, sizeof(double));
+    for (int t = 0; t < nT; ++t)
+        for (int mu = 0; mu < nmodes; ++mu)
+            if (omega[mu] > 0.0) occ[(size_t)t * nmodes + mu] = 1.0 / expm1(hk * omega[mu] / T[t]);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int it = 0; it < ntargets; ++it) {
+        const int mu = targets[it];
+        double sum[8], comp[8];
+        for (int t = 0; t < nT && t < 8; ++t) { sum[t] = 0.0; comp[t] = 0.0; }
+        int64_t cnt[2] = {0, 0};
+        if (omega[mu] > 0.0) {
+            const int iq = mu / nb;
+            for (int ch = 0; ch < 2; ++ch) {
+                const int s1 = ch == 0 ? +1 : -1;
+                for (int iq1 = 0; iq1 < N; ++iq1) {
+                    /* q'' = q +- q' folded into the grid */
+                    int a[3], b[3], r[3];
+                    qtriple(&m, iq, a); qtriple(&m, iq1, b);
+                    for (int d = 0; d < 3; ++d) r[d] = imod(a[d] + s1 * b[d], m.g[d]);
+                    const int iq2 = r[0] + m.g[0] * (r[1] + m.g[1] * r[2]);
+                    for (int j1 = 0; j1 < nb; ++j1) {
+                        const int mu1 = iq1 * nb + j1;
+                        if (omega[mu1] <= 0.0) continue;
+                        for (int j2 = 0; j2 < nb; ++j2) {
+                            const int mu2 = iq2 * nb + j2;
+                            if (omega[mu2] <= 0.0) continue;
+                            const double w = omega[mu], w1 = omega[mu1], w2 = omega[mu2];
+                            const double aw = s1 > 0 ? w + w1 : w - w1;
+                            const double dw = aw - w2;
+                            const double *v1 = vel + 3 * (size_t)mu1, *v2 = vel + 3 * (size_t)mu2;
+                            const double dx = v1[0] - v2[0], dy = v1[1] - v2[1], dz = v1[2] - v2[2];
+                            const double s2 = (dx * dx + dy * dy) + dz * dz;
+                            if (!(dw * dw <= c_win * s2)) continue;
+                            cnt[ch] += 1;
+                            const int md[3] = {mu, mu1, mu2};
+                            const int sg[3] = {+1, s1, -1};
+                            const cplx V = v3_general(&m, n3, atoms, cells, phi, md, sg);
+                            const double v2abs = creal(V) * creal(V) + cimag(V) * cimag(V);
+                            const double delta = oracle_delta(dw, c_sig * s2, sigma_min);
+                            for (int t = 0; t < nT && t < 8; ++t) {
+                                const double *n0 = occ + (size_t)t * nmodes;
+                                const double f = ch == 0 ? n0[mu1] - n0[mu2] : n0[mu1] + n0[mu2] + 1.0;
+                                const double G = C3 * f * v2abs * delta / (w * w1 * w2);
+                                neumaier(&sum[t], &comp[t], (ch == 0 ? 1.0 : 0.5) * G / (double)N);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        for (int t = 0; t < nT && t < 8; ++t) rates[(size_t)t * ntargets + it] = sum[t] + comp[t];
+        if (counts) { counts[2 * (size_t)it] = cnt[0]; counts[2 * (size_t)it + 1] = cnt[1]; }
+    }
+    free(occ);
+    model_free(&m);
+    return 0;
+}
