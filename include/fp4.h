@@ -157,6 +157,35 @@ int fp4_last_stats(const fp4_ctx *ctx, int64_t *processes, int64_t *candidates,
  * first to last kernel. */
 int fp4_last_timing(const fp4_ctx *ctx, double *ms_main, double *ms_total);
 
+/* ---------------------------------------------------------------- three-phonon rate
+ * Three-phonon RTA rate (Eq. tao0 three-phonon bracket, Eq. 3phgamma, Eq. V3), used as an
+ * input feature of the learned surrogate:
+ *   1/tau3(lambda) = (1/N) [ sum G+ + 1/2 sum G- ],  q'' = q +- q' folded into the grid,
+ *   G+ = (hbar pi/4) (n' - n'') |V+|^2 delta(w + w' - w'') / (w w' w''),
+ *   G- = (hbar pi/4) (n' + n'' + 1) |V-|^2 delta(w - w' - w'') / (w w' w''),
+ * with the same adaptive Gaussian (sigma = scalebroad |v' - v''| dq), window, sigma floor
+ * and inactive-mode rules as the four-phonon rate.  Computed in FP64. */
+
+/* Third-order force constants (copied; the caller keeps ownership).
+ *   atoms [n][3]       basis indices (i, j, k), i of the home cell
+ *   cells [n][2][3]    integer lattice coordinates of the cells of atoms j and k,
+ *                      each component in [-64, 64]
+ *   phi   [n][27]      eV/Angstrom^3, index (alpha*3 + beta)*3 + gamma
+ * 1 <= n <= 2^16.  Requires fp4_load_lattice first. */
+int fp4_load_fc3(fp4_ctx *ctx, int32_t ntrip, const int32_t *atoms, const int32_t *cells,
+                 const double *phi);
+
+/* Synchronous three-phonon rates.
+ *   T[nT]        temperatures (K), 1 <= nT <= 8, each > 0;  scalebroad > 0
+ *   targets      host [ntargets] mode ids in [0, nq*nb), or NULL for every mode
+ *                (ntargets ignored)
+ *   rates        host [nT][nt] 1/ps (required), nt = ntargets or nq*nb
+ *   counts       host [nt][2] kept processes of the + and - channels, or NULL
+ * Requires fp4_load_lattice, fp4_load_modes and fp4_load_fc3. */
+int fp4_compute_rates3(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                       const int32_t *targets, int32_t ntargets, double *rates,
+                       int64_t *counts);
+
 /* ---------------------------------------------------------------- batched instances
  * Several crystals (uneven branch counts, grids, quartet lists) evaluated by one captured HIP
  * graph: per instance occupations and precontraction, one persistent kernel per branch-count

@@ -40,7 +40,8 @@ EXPORTED = [
     "fp4_batch_destroy", "fp4_batch_add", "fp4_batch_compute", "fp4_batch_last_timing",
     "fp4_batch_last_error", "fp4_autotune", "fp4_mlp_create", "fp4_mlp_destroy",
     "fp4_mlp_last_error", "fp4_mlp_num_params", "fp4_mlp_get_params", "fp4_mlp_set_params",
-    "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict",
+    "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict", "fp4_load_fc3",
+    "fp4_compute_rates3",
 ]
 
 _lib = None
@@ -68,6 +69,8 @@ def lib():
         L.fp4_load_modes.argtypes = [P, i32, i32, P, P, P]
         L.fp4_load_fc4.argtypes = [P, i32, P, P, P]
         L.fp4_set_param.argtypes = [P, i32, f64]
+        L.fp4_load_fc3.argtypes = [P, i32, P, P, P]
+        L.fp4_compute_rates3.argtypes = [P, P, i32, f64, P, i32, P, P]
         L.fp4_compute_rates4.argtypes = [P, P, i32, f64, u32, i32, P, P, P]
         L.fp4_compute_rates4_subset.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P]
         L.fp4_compute_rates4_async.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
@@ -168,6 +171,27 @@ class Context:
         cl = np.ascontiguousarray(cells, dtype=np.int32)
         ph = np.ascontiguousarray(phi, dtype=np.float64)
         self._check(self._L.fp4_load_fc4(self._h, at.shape[0], _p(at), _p(cl), _p(ph)), "fp4_load_fc4")
+
+    def load_fc3(self, atoms, cells, phi):
+        at = np.ascontiguousarray(atoms, dtype=np.int32)
+        cl = np.ascontiguousarray(cells, dtype=np.int32)
+        ph = np.ascontiguousarray(phi, dtype=np.float64)
+        self._check(self._L.fp4_load_fc3(self._h, at.shape[0], _p(at), _p(cl), _p(ph)), "fp4_load_fc3")
+
+    def compute_rates3(self, T, scalebroad=1.0, targets=None, counts=True):
+        """Three-phonon rates (Eq. 3phgamma): (rates [nT][nt], counts [nt][2] or None)."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        if targets is None:
+            nt = self.nq * self.nb
+        else:
+            targets = np.ascontiguousarray(targets, dtype=np.int32)
+            nt = len(targets)
+        rates = np.zeros((len(T), nt))
+        cnt = np.zeros((nt, 2), dtype=np.int64) if counts else None
+        rc = self._L.fp4_compute_rates3(self._h, _p(T), len(T), float(scalebroad), _p(targets),
+                                        nt, _p(rates), _p(cnt))
+        self._check(rc, "fp4_compute_rates3")
+        return rates, cnt
 
     def load_instance(self, inst, dq=0.0, phi_scale=1.0):
         self.load_lattice(inst.cr.A, inst.grid, inst.cr.mass, dq)

@@ -37,6 +37,13 @@ double c4_prefactor() {
   return hbar * hbar * kPi / 8.0 * kv * kv * 1.0e-72;
 }
 
+// Eq. 3phgamma prefactor hbar pi / 4 for V in eV/(A^3 amu^1.5), same units otherwise.
+double c3_prefactor() {
+  const double hbar = kH / (2.0 * kPi);
+  const double kv = kEV / (1e-30 * kAMU * std::sqrt(kAMU));
+  return hbar * kPi / 4.0 * kv * kv * 1.0e-60;
+}
+
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
@@ -60,6 +67,11 @@ struct fp4_ctx {
   double dq = 0.0;
   // modes / fc4 loaded flags
   bool have_modes = false, have_fc4 = false, tables_dirty = true;
+  // third-order list (three-phonon feature), regrouped by atom pair (j, k) and d = Rj - Rk
+  bool have_fc3 = false, tables3_dirty = true;
+  int n3 = 0, nd3 = 0, nrk3 = 0;
+  std::vector<int> jk3_start, t3_i, t3_d, t3_rk, d3vec, rk3vec;
+  std::vector<double> t3_phi;
   // parameters
   double window_w = 2.0, sigma_min = 1e-4;
   int qchunk = 0, profile = 0;
@@ -74,6 +86,7 @@ struct fp4_ctx {
   DevBuf d_g_d, d_kl, d_cs, d_cj, d_ca, d_cq, d_qi, d_qb, d_qphi, d_avec, d_bvec, d_dvec;
   DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
   DevBuf d_rates, d_rch, d_counts, d_quads, d_tslot, d_V;
+  DevBuf d3_jk, d3_ti, d3_td, d3_trk, d3_phi, d3_rkv, d3_dv, d3_PH3, d3_U, d3_targets, d3_rates, d3_counts;
 
   // statistics / timing of the last call
   long long st_processes = 0, st_candidates = 0, st_blocks = 0;
@@ -441,7 +454,10 @@ void fp4_destroy(fp4_ctx *ctx) {
                    &ctx->d_cq, &ctx->d_qi, &ctx->d_qb, &ctx->d_qphi, &ctx->d_avec, &ctx->d_bvec,
                    &ctx->d_dvec, &ctx->d_T, &ctx->d_occ, &ctx->d_iocc, &ctx->d_targets,
                    &ctx->d_U, &ctx->d_partial, &ctx->d_pcount, &ctx->d_blocks, &ctx->d_rates,
-                   &ctx->d_rch, &ctx->d_counts, &ctx->d_quads, &ctx->d_tslot, &ctx->d_V};
+                   &ctx->d_rch, &ctx->d_counts, &ctx->d_quads, &ctx->d_tslot, &ctx->d_V,
+                   &ctx->d3_jk, &ctx->d3_ti, &ctx->d3_td, &ctx->d3_trk, &ctx->d3_phi,
+                   &ctx->d3_rkv, &ctx->d3_dv, &ctx->d3_PH3, &ctx->d3_U, &ctx->d3_targets,
+                   &ctx->d3_rates, &ctx->d3_counts};
   for (DevBuf *b : all) release(*b);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -487,7 +503,9 @@ int fp4_load_lattice(fp4_ctx *ctx, const double A[9], const int32_t grid[3], int
     ctx->have_lattice = true;
     ctx->have_modes = false;
     ctx->have_fc4 = false;
+    ctx->have_fc3 = false;
     ctx->tables_dirty = true;
+    ctx->tables3_dirty = true;
     ctx->err.clear();
     return FP4_OK;
   } catch (const std::bad_alloc &) {
@@ -766,6 +784,189 @@ int fp4_debug_matrix_elements(fp4_ctx *ctx, int32_t n, const int32_t *quads, int
     FP4_HIP(ctx, fp4::launch_debug_v(c, (const int *)ctx->d_quads.p, n, (const int *)ctx->d_tslot.p, ctx->d_U.p, fp32, (double2 *)ctx->d_V.p, ctx->stream));
     FP4_HIP(ctx, hipMemcpyAsync(V, ctx->d_V.p, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
     FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_load_fc3(fp4_ctx *ctx, int32_t ntrip, const int32_t *atoms, const int32_t *cells,
+                 const double *phi) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (!ctx->have_lattice) return ctx->fail(FP4_E_STATE, "fp4_load_lattice must come first");
+    if (ntrip < 1 || ntrip > (1 << 16)) return ctx->fail(FP4_E_INVAL, "need 1 <= ntrip <= 2^16");
+    if (!atoms || !cells || !phi) return ctx->fail(FP4_E_INVAL, "null pointer argument");
+    for (int i = 0; i < 3 * ntrip; ++i)
+      if (atoms[i] < 0 || atoms[i] >= ctx->nat) return ctx->fail(FP4_E_INVAL, "triplet atom index out of range");
+    for (int i = 0; i < 6 * ntrip; ++i)
+      if (cells[i] < -64 || cells[i] > 64) return ctx->fail(FP4_E_INVAL, "triplet cell coordinate outside [-64, 64]");
+    if (!finite_all(phi, (size_t)27 * ntrip)) return ctx->fail(FP4_E_INVAL, "force constants contain NaN or Inf");
+    using V3 = std::array<int, 3>;
+    std::map<V3, int> dmap, rmap;
+    auto intern = [](std::map<V3, int> &m, const V3 &v) {
+      auto it = m.find(v);
+      if (it != m.end()) return it->second;
+      const int id = (int)m.size();
+      m.emplace(v, id);
+      return id;
+    };
+    struct T3 {
+      int i, j, k, d, rk, n;
+    };
+    std::vector<T3> ts(ntrip);
+    for (int n = 0; n < ntrip; ++n) {
+      const int32_t *at = atoms + 3 * n, *cl = cells + 6 * n;
+      const V3 d{cl[0] - cl[3], cl[1] - cl[4], cl[2] - cl[5]};
+      const V3 rk{cl[3], cl[4], cl[5]};
+      ts[n] = T3{at[0], at[1], at[2], intern(dmap, d), intern(rmap, rk), n};
+    }
+    std::sort(ts.begin(), ts.end(), [](const T3 &x, const T3 &y) {
+      return std::tie(x.j, x.k, x.d, x.i, x.rk, x.n) < std::tie(y.j, y.k, y.d, y.i, y.rk, y.n);
+    });
+    const int nat = ctx->nat;
+    ctx->n3 = ntrip;
+    ctx->jk3_start.assign(nat * nat + 1, 0);
+    ctx->t3_i.resize(ntrip);
+    ctx->t3_d.resize(ntrip);
+    ctx->t3_rk.resize(ntrip);
+    ctx->t3_phi.resize((size_t)27 * ntrip);
+    for (int p = 0; p < ntrip; ++p) {
+      ctx->t3_i[p] = ts[p].i;
+      ctx->t3_d[p] = ts[p].d;
+      ctx->t3_rk[p] = ts[p].rk;
+      std::memcpy(&ctx->t3_phi[(size_t)27 * p], phi + (size_t)27 * ts[p].n, 27 * sizeof(double));
+    }
+    // jk3_start[jk] = first triplet whose pair index j*nat + k is >= jk
+    for (int jk = 0, p = 0; jk <= nat * nat; ++jk) {
+      while (p < ntrip && ts[p].j * nat + ts[p].k < jk) ++p;
+      ctx->jk3_start[jk] = p;
+    }
+    auto flat = [](const std::map<V3, int> &m) {
+      std::vector<int> v(3 * m.size());
+      for (auto &kv : m)
+        for (int x = 0; x < 3; ++x) v[3 * kv.second + x] = kv.first[x];
+      return v;
+    };
+    ctx->d3vec = flat(dmap);
+    ctx->rk3vec = flat(rmap);
+    ctx->nd3 = (int)dmap.size();
+    ctx->nrk3 = (int)rmap.size();
+    (void)hipSetDevice(ctx->device);
+    int rc;
+    if ((rc = upload(ctx, ctx->d3_jk, ctx->jk3_start.data(), ctx->jk3_start.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d3_ti, ctx->t3_i.data(), ctx->t3_i.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d3_td, ctx->t3_d.data(), ctx->t3_d.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d3_trk, ctx->t3_rk.data(), ctx->t3_rk.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d3_phi, ctx->t3_phi.data(), ctx->t3_phi.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d3_dv, ctx->d3vec.data(), ctx->d3vec.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d3_rkv, ctx->rk3vec.data(), ctx->rk3vec.size()))) return rc;
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->have_fc3 = true;
+    ctx->tables3_dirty = true;
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_compute_rates3(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                       const int32_t *targets, int32_t ntargets, double *rates,
+                       int64_t *counts) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (!ctx->have_lattice || !ctx->have_modes || !ctx->have_fc3)
+      return ctx->fail(FP4_E_STATE, "fp4_compute_rates3 needs fp4_load_lattice, fp4_load_modes and fp4_load_fc3");
+    if (!T || nT < 1 || nT > 8) return ctx->fail(FP4_E_INVAL, "need 1 <= nT <= 8 temperatures");
+    for (int i = 0; i < nT; ++i)
+      if (!(std::isfinite(T[i]) && T[i] > 0.0)) return ctx->fail(FP4_E_INVAL, "temperatures must be finite and > 0");
+    if (!(std::isfinite(scalebroad) && scalebroad > 0.0)) return ctx->fail(FP4_E_INVAL, "scalebroad must be finite and > 0");
+    if (!rates) return ctx->fail(FP4_E_INVAL, "rates output is required");
+    (void)hipSetDevice(ctx->device);
+    const int nmodes = ctx->N * ctx->nb;
+    std::vector<int> tl;
+    int nt;
+    if (targets) {
+      if (ntargets < 1 || ntargets > nmodes) return ctx->fail(FP4_E_INVAL, "need 1 <= ntargets <= nq*nb");
+      tl.assign(targets, targets + ntargets);
+      for (int v : tl)
+        if (v < 0 || v >= nmodes) return ctx->fail(FP4_E_INVAL, "target mode id out of range");
+      nt = ntargets;
+    } else {
+      nt = nmodes;
+      tl.resize(nt);
+      for (int i = 0; i < nt; ++i) tl[i] = i;
+    }
+    int rc;
+    if ((rc = ensure_tables(ctx))) return rc;
+    if (ctx->tables3_dirty) {
+      if ((rc = ensure(ctx, ctx->d3_PH3, (size_t)ctx->nd3 * ctx->N * sizeof(double2)))) return rc;
+      fp4::Crystal c0 = make_crystal(ctx);
+      FP4_HIP(ctx, fp4::launch_tables3(c0, (const int *)ctx->d3_dv.p, ctx->nd3, (double2 *)ctx->d3_PH3.p, ctx->stream));
+      ctx->tables3_dirty = false;
+    }
+    if ((rc = upload(ctx, ctx->d3_targets, tl.data(), tl.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_T, T, (size_t)nT))) return rc;
+    if ((rc = ensure(ctx, ctx->d_occ, (size_t)nmodes * nT * sizeof(double)))) return rc;
+    if ((rc = ensure(ctx, ctx->d_iocc, (size_t)nmodes * nT * sizeof(double)))) return rc;
+    if ((rc = ensure(ctx, ctx->d3_rates, (size_t)nT * nt * sizeof(double)))) return rc;
+    if ((rc = ensure(ctx, ctx->d3_counts, (size_t)nt * 2 * sizeof(long long)))) return rc;
+    fp4::Crystal c = make_crystal(ctx);
+    FP4_HIP(ctx, fp4::launch_occupations(c, (const double *)ctx->d_T.p, nT, hbar_over_kb_kps(),
+                                         (double *)ctx->d_occ.p, (double *)ctx->d_iocc.p, ctx->stream));
+    fp4::Fc3Dev f{};
+    f.n3 = ctx->n3;
+    f.nd3 = ctx->nd3;
+    f.nrk = ctx->nrk3;
+    f.jk_start = (const int *)ctx->d3_jk.p;
+    f.t_i = (const int *)ctx->d3_ti.p;
+    f.t_d = (const int *)ctx->d3_td.p;
+    f.t_rk = (const int *)ctx->d3_trk.p;
+    f.t_phi = (const double *)ctx->d3_phi.p;
+    f.rk_vec = (const int *)ctx->d3_rkv.p;
+    f.PH3 = (const double2 *)ctx->d3_PH3.p;
+    fp4::Rate3Args a{};
+    const double wsb = ctx->window_w * scalebroad;
+    a.c_win = (wsb * ctx->dq) * (wsb * ctx->dq);
+    a.c_sig = (scalebroad * ctx->dq) * (scalebroad * ctx->dq);
+    a.c_min = ctx->sigma_min * ctx->sigma_min;
+    a.kpref = c3_prefactor() / (double)ctx->N;
+    a.nT = nT;
+    a.occ = (const double *)ctx->d_occ.p;
+    a.targets = (const int *)ctx->d3_targets.p;
+    a.nt_total = nt;
+    a.rates = (double *)ctx->d3_rates.p;
+    a.counts = (long long *)ctx->d3_counts.p;
+    const size_t per_target = (size_t)ctx->n3 * 9 * sizeof(double2);
+    const int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, ((size_t)256 << 20) / per_target));
+    if ((rc = ensure(ctx, ctx->d3_U, (size_t)batch * per_target))) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profile) {
+      e0 = pool_event(ctx, 0);
+      e1 = pool_event(ctx, 1);
+      if (!e0 || !e1) return ctx->fail(FP4_E_DEVICE, "hipEventCreate failed");
+      FP4_HIP(ctx, hipEventRecord(e0, ctx->stream));
+    }
+    for (int t0 = 0; t0 < nt; t0 += batch) {
+      const int nbt = std::min(batch, nt - t0);
+      FP4_HIP(ctx, fp4::launch_precontract3(c, f, (const int *)ctx->d3_targets.p + t0, nbt,
+                                            (double2 *)ctx->d3_U.p, ctx->stream));
+      a.t0 = t0;
+      FP4_HIP(ctx, fp4::launch_rates3(c, f, a, (const double2 *)ctx->d3_U.p, nbt, ctx->stream));
+    }
+    if (ctx->profile) FP4_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    FP4_HIP(ctx, hipMemcpyAsync(rates, ctx->d3_rates.p, (size_t)nT * nt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (counts)
+      FP4_HIP(ctx, hipMemcpyAsync(counts, ctx->d3_counts.p, (size_t)nt * 2 * sizeof(long long), hipMemcpyDeviceToHost, ctx->stream));
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->profile) {
+      float ms = 0.f;
+      FP4_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+      ctx->ms_main = ms;
+      ctx->ms_total = ms;
+    }
     ctx->err.clear();
     return FP4_OK;
   } catch (const std::bad_alloc &) {

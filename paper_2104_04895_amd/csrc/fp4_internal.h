@@ -72,6 +72,32 @@ struct BatchInst {
   long long item0;
 };
 
+// Device-resident regrouped third-order force constants.  Triplet n has atoms (i, j, k)
+// and cells (0, Rj, Rk); triplets are ordered by the atom pair (j, k), then by d = Rj - Rk.
+struct Fc3Dev {
+  int n3, nd3, nrk;
+  const int *jk_start;      // [nat*nat + 1] first triplet of atom pair (j, k)
+  const int *t_i;           // [n3] slot-1 atom i
+  const int *t_d;           // [n3] index of d
+  const int *t_rk;          // [n3] index of Rk
+  const double *t_phi;      // [n3][27]
+  const int *rk_vec;        // [nrk][3]
+  const double2 *PH3;       // [nd3][N] exp(i q.d)
+};
+
+// Per-call parameters of the three-phonon rate kernel.
+struct Rate3Args {
+  double c_win, c_sig, c_min;
+  double kpref;             // (hbar pi / 4) / N
+  int nT;
+  const double *occ;        // [nT][N*nb]
+  const int *targets;       // [nt_total] mode ids
+  int nt_total;
+  int t0;                   // first target of this launch
+  double *rates;            // [nT][nt_total]
+  long long *counts;        // [nt_total][2] (nullable)
+};
+
 // launchers (fp4_kernels.hip)
 hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
@@ -91,5 +117,13 @@ size_t batch_lds_bytes(const Crystal &c, int fp32, int nT);
 hipError_t launch_batch(const BatchInst *insts, int ninst, long long total,
                         unsigned long long *counter, size_t lds, int fp32, int nb, int nT,
                         int *grid_out, hipStream_t s);
+
+// launchers (fp4_rates3.hip)
+hipError_t launch_tables3(const Crystal &c, const int *dvec, int nd, double2 *PH3, hipStream_t s);
+hipError_t launch_precontract3(const Crystal &c, const Fc3Dev &f, const int *targets, int nt,
+                               double2 *U, hipStream_t s);
+size_t rates3_lds_bytes(int nT);
+hipError_t launch_rates3(const Crystal &c, const Fc3Dev &f, const Rate3Args &a,
+                         const double2 *U, int nblocks, hipStream_t s);
 
 }  // namespace fp4
