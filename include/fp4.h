@@ -59,6 +59,9 @@ extern "C" {
 #define FP4_PARAM_PROFILE 4       /* 1: time every kernel with HIP events (fp4_last_timing) */
 
 /* channel bits of the process mask (Eq. 4phgamma): recombination, redistribution, splitting */
+/* number of surrogate input features per (temperature, mode) row */
+#define FP4_NFEAT 18
+
 #define FP4_PP 1u
 #define FP4_PM 2u
 #define FP4_MM 4u
@@ -185,6 +188,22 @@ int fp4_load_fc3(fp4_ctx *ctx, int32_t ntrip, const int32_t *atoms, const int32_
 int fp4_compute_rates3(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
                        const int32_t *targets, int32_t ntargets, double *rates,
                        int64_t *counts);
+
+/* Input features of the learned surrogate for every (temperature, target mode) pair:
+ * row (t, i) of X [nT][nt][FP4_NFEAT] (FP32) holds
+ *   0  ln w (rad/ps)            1  ln(|v| + 0.01) (A/ps)     2..13  one-hot branch j (< 12)
+ *   14 ln n0(w, T)              15 ln(1/tau3 + 1e-8) (1/ps, Eq. 3phgamma, computed here)
+ *   16 ln(T / 300 K)            17 ln(g4 + 1e-30), g4 = sum of |U|^2 over the slot-1
+ *                                  precontraction of the fourth-order list with the mode's
+ *                                  eigenvector and phase (Eq. V4), eV^2/(A^8 amu)
+ * Inactive modes (w <= 0) get 0 for their logarithms.  With shift and scale (both non-NULL,
+ * FP4_NFEAT floats each) every entry is standardised to (f - shift) * scale.
+ *   targets  host [ntargets] mode ids, or NULL for every mode (ntargets ignored)
+ *   rates3   host [nT][nt] three-phonon rates used for feature 15, or NULL
+ * Requires fp4_load_lattice, fp4_load_modes, fp4_load_fc4 and fp4_load_fc3. */
+int fp4_surrogate_features(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                           const int32_t *targets, int32_t ntargets, const float *shift,
+                           const float *scale, float *X, double *rates3);
 
 /* ---------------------------------------------------------------- batched instances
  * Several crystals (uneven branch counts, grids, quartet lists) evaluated by one captured HIP

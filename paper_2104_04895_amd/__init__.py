@@ -41,8 +41,9 @@ EXPORTED = [
     "fp4_batch_last_error", "fp4_autotune", "fp4_mlp_create", "fp4_mlp_destroy",
     "fp4_mlp_last_error", "fp4_mlp_num_params", "fp4_mlp_get_params", "fp4_mlp_set_params",
     "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict", "fp4_load_fc3",
-    "fp4_compute_rates3",
+    "fp4_compute_rates3", "fp4_surrogate_features",
 ]
+FP4_NFEAT = 18
 
 _lib = None
 
@@ -71,6 +72,7 @@ def lib():
         L.fp4_set_param.argtypes = [P, i32, f64]
         L.fp4_load_fc3.argtypes = [P, i32, P, P, P]
         L.fp4_compute_rates3.argtypes = [P, P, i32, f64, P, i32, P, P]
+        L.fp4_surrogate_features.argtypes = [P, P, i32, f64, P, i32, P, P, P, P]
         L.fp4_compute_rates4.argtypes = [P, P, i32, f64, u32, i32, P, P, P]
         L.fp4_compute_rates4_subset.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P]
         L.fp4_compute_rates4_async.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
@@ -192,6 +194,25 @@ class Context:
                                         nt, _p(rates), _p(cnt))
         self._check(rc, "fp4_compute_rates3")
         return rates, cnt
+
+    def surrogate_features(self, T, scalebroad=1.0, targets=None, shift=None, scale=None):
+        """Surrogate input rows X [nT][nt][FP4_NFEAT] (float32) and the three-phonon rates
+        [nT][nt] they were built from."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        if targets is None:
+            nt = self.nq * self.nb
+        else:
+            targets = np.ascontiguousarray(targets, dtype=np.int32)
+            nt = len(targets)
+        X = np.zeros((len(T), nt, FP4_NFEAT), dtype=np.float32)
+        r3 = np.zeros((len(T), nt))
+        if shift is not None:
+            shift = np.ascontiguousarray(shift, dtype=np.float32)
+            scale = np.ascontiguousarray(scale, dtype=np.float32)
+        rc = self._L.fp4_surrogate_features(self._h, _p(T), len(T), float(scalebroad), _p(targets),
+                                            nt, _p(shift), _p(scale), _p(X), _p(r3))
+        self._check(rc, "fp4_surrogate_features")
+        return X, r3
 
     def load_instance(self, inst, dq=0.0, phi_scale=1.0):
         self.load_lattice(inst.cr.A, inst.grid, inst.cr.mass, dq)

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfp4.so")
 SOURCES = [os.path.join(HERE, "csrc", "fp4_api.cpp"), os.path.join(HERE, "csrc", "fp4_kernels.hip"),
-           os.path.join(HERE, "csrc", "fp4_mlp.hip"), os.path.join(HERE, "csrc", "fp4_rates3.hip")]
+           os.path.join(HERE, "csrc", "fp4_mlp.hip"), os.path.join(HERE, "csrc", "fp4_rates3.hip"),
+           os.path.join(HERE, "csrc", "fp4_features.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -87,6 +87,7 @@ struct fp4_ctx {
   DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
   DevBuf d_rates, d_rch, d_counts, d_quads, d_tslot, d_V;
   DevBuf d3_jk, d3_ti, d3_td, d3_trk, d3_phi, d3_rkv, d3_dv, d3_PH3, d3_U, d3_targets, d3_rates, d3_counts;
+  DevBuf df_g4, df_X, df_shift;
 
   // statistics / timing of the last call
   long long st_processes = 0, st_candidates = 0, st_blocks = 0;
@@ -457,7 +458,7 @@ void fp4_destroy(fp4_ctx *ctx) {
                    &ctx->d_rch, &ctx->d_counts, &ctx->d_quads, &ctx->d_tslot, &ctx->d_V,
                    &ctx->d3_jk, &ctx->d3_ti, &ctx->d3_td, &ctx->d3_trk, &ctx->d3_phi,
                    &ctx->d3_rkv, &ctx->d3_dv, &ctx->d3_PH3, &ctx->d3_U, &ctx->d3_targets,
-                   &ctx->d3_rates, &ctx->d3_counts};
+                   &ctx->d3_rates, &ctx->d3_counts, &ctx->df_g4, &ctx->df_X, &ctx->df_shift};
   for (DevBuf *b : all) release(*b);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -872,76 +873,106 @@ int fp4_load_fc3(fp4_ctx *ctx, int32_t ntrip, const int32_t *atoms, const int32_
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the three-phonon rate and the feature builder; fills the target list.
+int rates3_args(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                const int32_t *targets, int32_t ntargets, std::vector<int> &tl) {
+  if (!ctx->have_lattice || !ctx->have_modes || !ctx->have_fc3)
+    return ctx->fail(FP4_E_STATE, "the three-phonon rate needs fp4_load_lattice, fp4_load_modes and fp4_load_fc3");
+  if (!T || nT < 1 || nT > 8) return ctx->fail(FP4_E_INVAL, "need 1 <= nT <= 8 temperatures");
+  for (int i = 0; i < nT; ++i)
+    if (!(std::isfinite(T[i]) && T[i] > 0.0)) return ctx->fail(FP4_E_INVAL, "temperatures must be finite and > 0");
+  if (!(std::isfinite(scalebroad) && scalebroad > 0.0)) return ctx->fail(FP4_E_INVAL, "scalebroad must be finite and > 0");
+  const int nmodes = ctx->N * ctx->nb;
+  if (targets) {
+    if (ntargets < 1 || ntargets > nmodes) return ctx->fail(FP4_E_INVAL, "need 1 <= ntargets <= nq*nb");
+    tl.assign(targets, targets + ntargets);
+    for (int v : tl)
+      if (v < 0 || v >= nmodes) return ctx->fail(FP4_E_INVAL, "target mode id out of range");
+  } else {
+    tl.resize(nmodes);
+    for (int i = 0; i < nmodes; ++i) tl[i] = i;
+  }
+  return FP4_OK;
+}
+
+// Enqueue the three-phonon rates of the targets tl on the context stream: device outputs
+// d3_rates [nT][nt], d3_counts [nt][2]; occupations left in d_occ, temperatures in d_T.
+int enqueue_rates3(fp4_ctx *ctx, const double *T, int nT, double scalebroad,
+                   const std::vector<int> &tl) {
+  const int nmodes = ctx->N * ctx->nb;
+  const int nt = (int)tl.size();
+  int rc;
+  if ((rc = ensure_tables(ctx))) return rc;
+  if (ctx->tables3_dirty) {
+    if ((rc = ensure(ctx, ctx->d3_PH3, (size_t)ctx->nd3 * ctx->N * sizeof(double2)))) return rc;
+    fp4::Crystal c0 = make_crystal(ctx);
+    FP4_HIP(ctx, fp4::launch_tables3(c0, (const int *)ctx->d3_dv.p, ctx->nd3, (double2 *)ctx->d3_PH3.p, ctx->stream));
+    ctx->tables3_dirty = false;
+  }
+  if ((rc = upload(ctx, ctx->d3_targets, tl.data(), tl.size()))) return rc;
+  if ((rc = upload(ctx, ctx->d_T, T, (size_t)nT))) return rc;
+  if ((rc = ensure(ctx, ctx->d_occ, (size_t)nmodes * nT * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_iocc, (size_t)nmodes * nT * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d3_rates, (size_t)nT * nt * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->d3_counts, (size_t)nt * 2 * sizeof(long long)))) return rc;
+  fp4::Crystal c = make_crystal(ctx);
+  FP4_HIP(ctx, fp4::launch_occupations(c, (const double *)ctx->d_T.p, nT, hbar_over_kb_kps(),
+                                       (double *)ctx->d_occ.p, (double *)ctx->d_iocc.p, ctx->stream));
+  fp4::Fc3Dev f{};
+  f.n3 = ctx->n3;
+  f.nd3 = ctx->nd3;
+  f.nrk = ctx->nrk3;
+  f.jk_start = (const int *)ctx->d3_jk.p;
+  f.t_i = (const int *)ctx->d3_ti.p;
+  f.t_d = (const int *)ctx->d3_td.p;
+  f.t_rk = (const int *)ctx->d3_trk.p;
+  f.t_phi = (const double *)ctx->d3_phi.p;
+  f.rk_vec = (const int *)ctx->d3_rkv.p;
+  f.PH3 = (const double2 *)ctx->d3_PH3.p;
+  fp4::Rate3Args a{};
+  const double wsb = ctx->window_w * scalebroad;
+  a.c_win = (wsb * ctx->dq) * (wsb * ctx->dq);
+  a.c_sig = (scalebroad * ctx->dq) * (scalebroad * ctx->dq);
+  a.c_min = ctx->sigma_min * ctx->sigma_min;
+  a.kpref = c3_prefactor() / (double)ctx->N;
+  a.nT = nT;
+  a.occ = (const double *)ctx->d_occ.p;
+  a.targets = (const int *)ctx->d3_targets.p;
+  a.nt_total = nt;
+  a.rates = (double *)ctx->d3_rates.p;
+  a.counts = (long long *)ctx->d3_counts.p;
+  const size_t per_target = (size_t)ctx->n3 * 9 * sizeof(double2);
+  const int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, ((size_t)256 << 20) / per_target));
+  if ((rc = ensure(ctx, ctx->d3_U, (size_t)batch * per_target))) return rc;
+  for (int t0 = 0; t0 < nt; t0 += batch) {
+    const int nbt = std::min(batch, nt - t0);
+    FP4_HIP(ctx, fp4::launch_precontract3(c, f, (const int *)ctx->d3_targets.p + t0, nbt,
+                                          (double2 *)ctx->d3_U.p, ctx->stream));
+    a.t0 = t0;
+    FP4_HIP(ctx, fp4::launch_rates3(c, f, a, (const double2 *)ctx->d3_U.p, nbt, ctx->stream));
+  }
+  return FP4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int fp4_compute_rates3(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
                        const int32_t *targets, int32_t ntargets, double *rates,
                        int64_t *counts) {
   if (!ctx) return FP4_E_INVAL;
   try {
-    if (!ctx->have_lattice || !ctx->have_modes || !ctx->have_fc3)
-      return ctx->fail(FP4_E_STATE, "fp4_compute_rates3 needs fp4_load_lattice, fp4_load_modes and fp4_load_fc3");
-    if (!T || nT < 1 || nT > 8) return ctx->fail(FP4_E_INVAL, "need 1 <= nT <= 8 temperatures");
-    for (int i = 0; i < nT; ++i)
-      if (!(std::isfinite(T[i]) && T[i] > 0.0)) return ctx->fail(FP4_E_INVAL, "temperatures must be finite and > 0");
-    if (!(std::isfinite(scalebroad) && scalebroad > 0.0)) return ctx->fail(FP4_E_INVAL, "scalebroad must be finite and > 0");
+    std::vector<int> tl;
+    int rc = rates3_args(ctx, T, nT, scalebroad, targets, ntargets, tl);
+    if (rc) return rc;
     if (!rates) return ctx->fail(FP4_E_INVAL, "rates output is required");
     (void)hipSetDevice(ctx->device);
-    const int nmodes = ctx->N * ctx->nb;
-    std::vector<int> tl;
-    int nt;
-    if (targets) {
-      if (ntargets < 1 || ntargets > nmodes) return ctx->fail(FP4_E_INVAL, "need 1 <= ntargets <= nq*nb");
-      tl.assign(targets, targets + ntargets);
-      for (int v : tl)
-        if (v < 0 || v >= nmodes) return ctx->fail(FP4_E_INVAL, "target mode id out of range");
-      nt = ntargets;
-    } else {
-      nt = nmodes;
-      tl.resize(nt);
-      for (int i = 0; i < nt; ++i) tl[i] = i;
-    }
-    int rc;
-    if ((rc = ensure_tables(ctx))) return rc;
-    if (ctx->tables3_dirty) {
-      if ((rc = ensure(ctx, ctx->d3_PH3, (size_t)ctx->nd3 * ctx->N * sizeof(double2)))) return rc;
-      fp4::Crystal c0 = make_crystal(ctx);
-      FP4_HIP(ctx, fp4::launch_tables3(c0, (const int *)ctx->d3_dv.p, ctx->nd3, (double2 *)ctx->d3_PH3.p, ctx->stream));
-      ctx->tables3_dirty = false;
-    }
-    if ((rc = upload(ctx, ctx->d3_targets, tl.data(), tl.size()))) return rc;
-    if ((rc = upload(ctx, ctx->d_T, T, (size_t)nT))) return rc;
-    if ((rc = ensure(ctx, ctx->d_occ, (size_t)nmodes * nT * sizeof(double)))) return rc;
-    if ((rc = ensure(ctx, ctx->d_iocc, (size_t)nmodes * nT * sizeof(double)))) return rc;
-    if ((rc = ensure(ctx, ctx->d3_rates, (size_t)nT * nt * sizeof(double)))) return rc;
-    if ((rc = ensure(ctx, ctx->d3_counts, (size_t)nt * 2 * sizeof(long long)))) return rc;
-    fp4::Crystal c = make_crystal(ctx);
-    FP4_HIP(ctx, fp4::launch_occupations(c, (const double *)ctx->d_T.p, nT, hbar_over_kb_kps(),
-                                         (double *)ctx->d_occ.p, (double *)ctx->d_iocc.p, ctx->stream));
-    fp4::Fc3Dev f{};
-    f.n3 = ctx->n3;
-    f.nd3 = ctx->nd3;
-    f.nrk = ctx->nrk3;
-    f.jk_start = (const int *)ctx->d3_jk.p;
-    f.t_i = (const int *)ctx->d3_ti.p;
-    f.t_d = (const int *)ctx->d3_td.p;
-    f.t_rk = (const int *)ctx->d3_trk.p;
-    f.t_phi = (const double *)ctx->d3_phi.p;
-    f.rk_vec = (const int *)ctx->d3_rkv.p;
-    f.PH3 = (const double2 *)ctx->d3_PH3.p;
-    fp4::Rate3Args a{};
-    const double wsb = ctx->window_w * scalebroad;
-    a.c_win = (wsb * ctx->dq) * (wsb * ctx->dq);
-    a.c_sig = (scalebroad * ctx->dq) * (scalebroad * ctx->dq);
-    a.c_min = ctx->sigma_min * ctx->sigma_min;
-    a.kpref = c3_prefactor() / (double)ctx->N;
-    a.nT = nT;
-    a.occ = (const double *)ctx->d_occ.p;
-    a.targets = (const int *)ctx->d3_targets.p;
-    a.nt_total = nt;
-    a.rates = (double *)ctx->d3_rates.p;
-    a.counts = (long long *)ctx->d3_counts.p;
-    const size_t per_target = (size_t)ctx->n3 * 9 * sizeof(double2);
-    const int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, ((size_t)256 << 20) / per_target));
-    if ((rc = ensure(ctx, ctx->d3_U, (size_t)batch * per_target))) return rc;
+    const int nt = (int)tl.size();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->profile) {
       e0 = pool_event(ctx, 0);
@@ -949,13 +980,7 @@ int fp4_compute_rates3(fp4_ctx *ctx, const double *T, int32_t nT, double scalebr
       if (!e0 || !e1) return ctx->fail(FP4_E_DEVICE, "hipEventCreate failed");
       FP4_HIP(ctx, hipEventRecord(e0, ctx->stream));
     }
-    for (int t0 = 0; t0 < nt; t0 += batch) {
-      const int nbt = std::min(batch, nt - t0);
-      FP4_HIP(ctx, fp4::launch_precontract3(c, f, (const int *)ctx->d3_targets.p + t0, nbt,
-                                            (double2 *)ctx->d3_U.p, ctx->stream));
-      a.t0 = t0;
-      FP4_HIP(ctx, fp4::launch_rates3(c, f, a, (const double2 *)ctx->d3_U.p, nbt, ctx->stream));
-    }
+    if ((rc = enqueue_rates3(ctx, T, nT, scalebroad, tl))) return rc;
     if (ctx->profile) FP4_HIP(ctx, hipEventRecord(e1, ctx->stream));
     FP4_HIP(ctx, hipMemcpyAsync(rates, ctx->d3_rates.p, (size_t)nT * nt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     if (counts)
@@ -967,6 +992,52 @@ int fp4_compute_rates3(fp4_ctx *ctx, const double *T, int32_t nT, double scalebr
       ctx->ms_main = ms;
       ctx->ms_total = ms;
     }
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_surrogate_features(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                           const int32_t *targets, int32_t ntargets, const float *shift,
+                           const float *scale, float *X, double *rates3) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    std::vector<int> tl;
+    int rc = rates3_args(ctx, T, nT, scalebroad, targets, ntargets, tl);
+    if (rc) return rc;
+    if (!ctx->have_fc4) return ctx->fail(FP4_E_STATE, "the surrogate features need fp4_load_fc4");
+    if (!X) return ctx->fail(FP4_E_INVAL, "X output is required");
+    if ((shift == nullptr) != (scale == nullptr)) return ctx->fail(FP4_E_INVAL, "give both shift and scale, or neither");
+    if (shift) {
+      for (int k = 0; k < FP4_NFEAT; ++k)
+        if (!std::isfinite(shift[k]) || !std::isfinite(scale[k])) return ctx->fail(FP4_E_INVAL, "shift and scale must be finite");
+    }
+    (void)hipSetDevice(ctx->device);
+    const int nt = (int)tl.size();
+    if ((rc = enqueue_rates3(ctx, T, nT, scalebroad, tl))) return rc;
+    if ((rc = ensure(ctx, ctx->df_g4, (size_t)nt * sizeof(double)))) return rc;
+    if ((rc = ensure(ctx, ctx->df_X, (size_t)nT * nt * FP4_NFEAT * sizeof(float)))) return rc;
+    float *d_shift = nullptr, *d_scale = nullptr;
+    if (shift) {
+      std::vector<float> ss(2 * FP4_NFEAT);
+      std::memcpy(ss.data(), shift, FP4_NFEAT * sizeof(float));
+      std::memcpy(ss.data() + FP4_NFEAT, scale, FP4_NFEAT * sizeof(float));
+      if ((rc = upload(ctx, ctx->df_shift, ss.data(), ss.size()))) return rc;
+      d_shift = (float *)ctx->df_shift.p;
+      d_scale = d_shift + FP4_NFEAT;
+    }
+    fp4::Crystal c = make_crystal(ctx);
+    FP4_HIP(ctx, fp4::launch_fc4_strength(c, (const int *)ctx->d3_targets.p, nt, (double *)ctx->df_g4.p, ctx->stream));
+    FP4_HIP(ctx, fp4::launch_features(c, (const int *)ctx->d3_targets.p, nt, (const double *)ctx->d_T.p, nT,
+                                      (const double *)ctx->d_occ.p, (const double *)ctx->d3_rates.p,
+                                      (const double *)ctx->df_g4.p, d_shift, d_scale,
+                                      (float *)ctx->df_X.p, ctx->stream));
+    FP4_HIP(ctx, hipMemcpyAsync(X, ctx->df_X.p, (size_t)nT * nt * FP4_NFEAT * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    if (rates3)
+      FP4_HIP(ctx, hipMemcpyAsync(rates3, ctx->d3_rates.p, (size_t)nT * nt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->err.clear();
     return FP4_OK;
   } catch (const std::bad_alloc &) {

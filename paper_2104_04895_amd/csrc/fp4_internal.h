@@ -126,4 +126,11 @@ size_t rates3_lds_bytes(int nT);
 hipError_t launch_rates3(const Crystal &c, const Fc3Dev &f, const Rate3Args &a,
                          const double2 *U, int nblocks, hipStream_t s);
 
+// launchers (fp4_features.hip)
+hipError_t launch_fc4_strength(const Crystal &c, const int *targets, int nt, double *g4,
+                               hipStream_t s);
+hipError_t launch_features(const Crystal &c, const int *targets, int nt, const double *T, int nT,
+                           const double *occ, const double *r3, const double *g4,
+                           const float *shift, const float *scale, float *X, hipStream_t s);
+
 }  // namespace fp4
