@@ -6,6 +6,12 @@ every mode of the 8x8x8 diamond-structure workload (3072 modes, second-shell FC4
 quartets, T = 300 and 1000 K, scalebroad 1, all three channels), inputs resident in HBM.
 
 Prints one JSON line.  `value` is kept four-phonon processes per second.
+
+``--surrogate`` runs the learned-surrogate workload instead: exact rates on sampled modes of
+12x12x12 grids of 8 seeded force-constant draws (T from 100 to 1200 K) train the network;
+inference covers every mode of a held-out 20x20x20 grid (48 000 modes) with exact fallback
+on flagged modes and a 2% audit.  Its JSON line reports the audit's relative error, the
+fallback rate and the speedup over the plain FP64 kernel.
 """
 from __future__ import annotations
 
@@ -48,6 +54,83 @@ def groups_and_combos(fc4):
     return len(g), len(c)
 
 
+def surrogate_main(args):
+    import synth
+    from synth.fc3 import random_fc3
+    import paper_2104_04895_amd as fp4
+    from paper_2104_04895_amd import surrogate as S
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    tg = (args.train_grid,) * 3
+    ig = (args.infer_grid,) * 3
+    T_train = [100.0, 200.0, 400.0, 700.0, 1000.0, 1200.0]
+    T_inf = [300.0, 700.0]
+
+    def load(grid, seed):
+        inst = synth.diamond_instance(grid, synth.configs.RC_SECOND, seed=seed)
+        fc3 = random_fc3(inst.cr, synth.configs.RC_FIRST, np.random.default_rng(seed + 500))
+        c = fp4.Context(0)
+        c.load_instance(inst)        # dq = the library's default (|det B| / N)^(1/3)
+        c.load_fc3(fc3.atoms, fc3.cells, fc3.phi)
+        return inst, c
+
+    rng = np.random.default_rng(0)
+    tr, ca = S.TrainSet(), S.TrainSet()
+    t_train_exact = 0.0
+    t0 = time.perf_counter()
+    for d in range(args.draws):
+        inst, c = load(tg, 1000 + d)
+        modes = rng.permutation(inst.nmodes)
+        n_tr = int(args.sample_frac * inst.nmodes)
+        n_ca = max(8, n_tr // 5)
+        X, y, te = S.collect(c, inst.omega, T_train, 1.0, modes[:n_tr])
+        tr.add(X, y)
+        X2, y2, te2 = S.collect(c, inst.omega, T_train, 1.0, modes[n_tr:n_tr + n_ca])
+        ca.add(X2, y2)
+        t_train_exact += te + te2
+        c.close()
+        log(f"draw {d}: {n_tr}+{n_ca} exact modes in {te + te2:.1f} s")
+    sur = S.Surrogate(seed=1)
+    X, y = tr.arrays()
+    t1 = time.perf_counter()
+    loss = sur.fit(X, y, epochs=args.epochs, batch=256, lr=1e-3)
+    t_fit = time.perf_counter() - t1
+    kappa = sur.calibrate(*ca.arrays())
+    log(f"trained on {len(y)} rows in {t_fit:.1f} s, loss {loss[0]:.3f} -> {loss[-1]:.3f}, "
+        f"kappa {kappa:.2f}")
+    seed = 1000 if not args.unseen_draw else 2000
+    inst, c = load(ig, seed)
+    log(f"inference grid {ig} ({inst.nmodes} modes) loaded; the exact fallback and audit follow")
+    rates, rep = S.infer(sur, c, inst.omega, T_inf, flag_sigma=args.flag_sigma,
+                         audit_frac=0.02, audit_seed=7, chunk=64,
+                         progress=lambda what, done, tot: log(f"{what} exact {done}/{tot}"))
+    c.close()
+    rep.pop("audit_modes")
+    rep.pop("flagged_modes")
+    out = {
+        "metric": "surrogate 4ph rates: audit rel. err vs exact, fallback rate, speedup over the plain FP64 kernel",
+        "value": rep["speedup_vs_exact_estimate"],
+        "unit": "x (time of the exact FP64 kernel on all modes, estimated from the audit's "
+                "per-mode time, over the whole surrogate pass)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "bf16-inference/f64-exact",
+        "data": "synthetic",
+        "config": {"workload": f"diamond-structure 2-atom cell, second-shell FC4, first-shell FC3; "
+                               f"train {args.draws} draws x {tg[0]}^3 grid ({args.sample_frac:.0%} of modes, "
+                               f"T=100..1200 K); infer {ig[0]}^3 grid of "
+                               + ("an unseen draw" if args.unseen_draw else "training draw 0")
+                               + ", T=300,700 K",
+                   "flag_sigma": args.flag_sigma, "audit_frac": 0.02, "epochs": args.epochs},
+        "training": {"rows": int(len(y)), "exact_seconds": t_train_exact, "fit_seconds": t_fit,
+                     "loss_first": float(loss[0]), "loss_last": float(loss[-1]), "kappa": kappa,
+                     "wall_seconds": time.perf_counter() - t0},
+        "report": rep,
+    }
+    print(json.dumps(out))
+    sur.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,12 +139,23 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 side measurement")
+    ap.add_argument("--surrogate", action="store_true", help="run the learned-surrogate workload")
+    ap.add_argument("--train-grid", type=int, default=12)
+    ap.add_argument("--infer-grid", type=int, default=20)
+    ap.add_argument("--draws", type=int, default=8)
+    ap.add_argument("--sample-frac", type=float, default=0.1)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--flag-sigma", type=float, default=0.15)
+    ap.add_argument("--unseen-draw", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the rate kernel runs on a single MI355X and "
               f"--gpus {args.gpus} is not supported (multi-GPU sharding is a design note).",
               file=sys.stderr)
         sys.exit(2)
+    if args.surrogate:
+        surrogate_main(args)
+        return
 
     import torch
     import synth

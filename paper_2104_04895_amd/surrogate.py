@@ -146,10 +146,29 @@ class Surrogate:
         self.net.close()
 
 
+def exact_chunked(ctx: Context, T, scalebroad, targets, precision=FP4_FP64, chunk=0,
+                  progress=None, what="exact"):
+    """Exact rates of `targets` in calls of at most `chunk` modes (0: one call), reporting
+    each finished call to `progress(what, done, total)`.  Returns (rates [nT][nt], seconds)."""
+    targets = np.asarray(targets, dtype=np.int32)
+    nT = len(np.atleast_1d(T))
+    out = np.zeros((nT, targets.size))
+    step = targets.size if chunk <= 0 else chunk
+    t0 = time.perf_counter()
+    for a in range(0, targets.size, max(step, 1)):
+        r, _, _ = ctx.compute_rates4(T, scalebroad, 7, precision, targets[a:a + step], counts=False)
+        out[:, a:a + step] = r
+        if progress:
+            progress(what, min(a + step, targets.size), targets.size)
+    return out, time.perf_counter() - t0
+
+
 def infer(sur: Surrogate, ctx: Context, omega, T, scalebroad=1.0, flag_sigma=0.2,
-          audit_frac=0.02, audit_seed=0, precision=FP4_FP64, bf16=True):
+          audit_frac=0.02, audit_seed=0, precision=FP4_FP64, bf16=True, chunk=0,
+          progress=None):
     """Rates of every mode of the context's grid: surrogate predictions, with flagged modes
-    and a random audit sample of the others recomputed by the exact kernel.
+    and a random audit sample of the others recomputed by the exact kernel (in calls of at
+    most `chunk` modes, each reported to `progress`).
 
     Returns (rates [nT][nq*nb], report dict)."""
     T = np.atleast_1d(np.asarray(T, np.float64))
@@ -175,23 +194,24 @@ def infer(sur: Surrogate, ctx: Context, omega, T, scalebroad=1.0, flag_sigma=0.2
     n_audit = min(max(n_audit, 1 if rest.size else 0), rest.size)
     audit = np.sort(rng.choice(rest, size=n_audit, replace=False)) if n_audit else np.zeros(0, int)
 
+    if progress:
+        progress(f"predicted {active.size} modes; flagged {int(flagged.sum())}, audit", 0,
+                 int(n_audit))
     rates = np.zeros((nT, nmodes))
     rates[:, active] = np.exp(mu)
     pred_audit = np.exp(mu[:, audit])
 
     t_audit = t_flag = 0.0
     if audit.size:
-        t0 = time.perf_counter()
-        ra, _, _ = ctx.compute_rates4(T, scalebroad, 7, precision, active[audit], counts=False)
-        t_audit = time.perf_counter() - t0
+        ra, t_audit = exact_chunked(ctx, T, scalebroad, active[audit], precision, chunk,
+                                    progress, "audit")
         rates[:, active[audit]] = ra
     else:
         ra = np.zeros((nT, 0))
     fl = np.flatnonzero(flagged)
     if fl.size:
-        t0 = time.perf_counter()
-        rf, _, _ = ctx.compute_rates4(T, scalebroad, 7, precision, active[fl], counts=False)
-        t_flag = time.perf_counter() - t0
+        rf, t_flag = exact_chunked(ctx, T, scalebroad, active[fl], precision, chunk, progress,
+                                   "flagged")
         rates[:, active[fl]] = rf
 
     # audit statistics: relative error of the predictions that were kept for every other mode
