@@ -309,26 +309,47 @@ __device__ __forceinline__ unsigned row_bits(const Crystal &c, const RateArgs &a
   return bits;
 }
 
+// What Gamma needs of a mode besides V: (v, w), 1/w and n0 at each temperature.
+template <int NT>
+struct ModeRec {
+  double4 m;
+  double iw;
+  double n[NT];
+};
+
+template <int NB, int NT>
+__device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs &a, int mu) {
+  ModeRec<NT> r;
+  r.m = c.mode4[mu];
+  r.iw = c.inv_omega[mu];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) r.n[t] = (t < a.nT) ? a.occ[(size_t)t * c.N * NB + mu] : 0.0;
+  return r;
+}
+
 // Gamma (Eq. 4phgamma) of the kept processes of one row and orientation, accumulated into
-// the lane's FP64 partial rates.  Vrow[cc] is V of the row's process with column cc.
+// the lane's FP64 partial rates.  Vrow[cc] is V of the row's process with column cc; rrec
+// is the row mode's record.  The record of the next kept column is fetched while the
+// current one is evaluated.
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void gamma_row(const Crystal &c, const RateArgs &a,
                                           const typename CT<R>::T *Vrow, unsigned bits,
-                                          int orient, int mur, int iqc, double aw, double kw,
-                                          const double (&invn)[NT], const double (&n1)[NT],
-                                          Acc<NT> &acc) {
+                                          int orient, const ModeRec<NT> &rrec, int iqc,
+                                          double aw, double kw, const double (&invn)[NT],
+                                          const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
   constexpr int S2 = (CH == 0) ? 1 : -1;
+  ModeRec<NT> nx = load_rec<NB, NT>(c, a, iqc * NB + __builtin_ctz(bits));
 #pragma unroll 1
-  for (int cc = 0; cc < NB; ++cc) {
-    if (!((bits >> cc) & 1u)) continue;
-    const int muc = iqc * NB + cc;
-    const int mu2 = orient == 0 ? mur : muc;
-    const int mu3 = orient == 0 ? muc : mur;
-    const double4 v2 = c.mode4[mu2];
-    const double4 v3 = c.mode4[mu3];
+  while (bits) {
+    const int cc = __builtin_ctz(bits);
+    bits &= bits - 1u;
+    const ModeRec<NT> col = nx;
+    if (bits) nx = load_rec<NB, NT>(c, a, iqc * NB + __builtin_ctz(bits));
+    const ModeRec<NT> &p2 = orient == 0 ? rrec : col;
+    const ModeRec<NT> &p3 = orient == 0 ? col : rrec;
     double dw, s2;
-    window_keep(add_signed(aw, v2.w, S2), v3.w, v2, v3, a.c_win, dw, s2);
+    window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
     const CR vv = Vrow[cc];
     const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
     const double sig2 = a.c_sig * s2;
@@ -338,12 +359,12 @@ __device__ __forceinline__ void gamma_row(const Crystal &c, const RateArgs &a,
       const double is2 = 1.0 / sig2;
       delta = exp(-(dw * dw) * is2) * (0.5641895835477563 * sqrt(is2));
     }
-    const double base = kw * c.inv_omega[mu2] * c.inv_omega[mu3] * v2abs * delta;
+    const double base = kw * p2.iw * p3.iw * v2abs * delta;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (t < a.nT) {
-        const double n2 = a.occ[(size_t)t * c.N * NB + mu2];
-        const double n3 = a.occ[(size_t)t * c.N * NB + mu3];
+        const double n2 = p2.n[t];
+        const double n3 = p3.n[t];
         double f;
         if (CH == 0) f = (1.0 + n1[t]) * (1.0 + n2) * n3;
         else if (CH == 1) f = (1.0 + n1[t]) * n2 * n3;
@@ -436,8 +457,9 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         // survivor loop is not unrolled
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
-        if (bA) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bA, 0, mur, iq3, aw, kw, invn, n1, acc);
-        if (bB) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bB, 1, mur, iq3, aw, kw, invn, n1, acc);
+        const ModeRec<NT> rrec = load_rec<NB, NT>(c, a, mur);
+        if (bA) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bA, 0, rrec, iq3, aw, kw, invn, n1, acc);
+        if (bB) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bB, 1, rrec, iq3, aw, kw, invn, n1, acc);
       }
     }
     wave_sync();
@@ -564,7 +586,7 @@ __global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
 // instance (the host orders the instances by cost per item, most expensive first).  Crystals
 // of different branch counts run as separate persistent kernels of the same graph.
 template <typename R, int NB, int NT>
-__global__ __launch_bounds__(256, 2) void k_rates_batch(const BatchInst *__restrict__ insts, int ninst,
+__global__ __launch_bounds__(256, 3) void k_rates_batch(const BatchInst *__restrict__ insts, int ninst,
                                                         long long total,
                                                         unsigned long long *counter) {
   extern __shared__ __align__(16) unsigned char smem[];
