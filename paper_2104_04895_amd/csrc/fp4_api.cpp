@@ -44,6 +44,9 @@ double c3_prefactor() {
   return hbar * kPi / 4.0 * kv * kv * 1.0e-60;
 }
 
+// MI355X deals work-groups to its 8 XCDs (each with its own L2) round-robin by blockIdx.
+constexpr int kXcds = 8;
+
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
@@ -249,6 +252,12 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
     if (nchunk < 1) nchunk = 1;
     if (nchunk > ctx->N) nchunk = ctx->N;
     qchunk = (int)((ctx->N + nchunk - 1) / nchunk);
+    // at most 16 q' per work-group, so that the ~96 work-groups resident on an XCD span
+    // few targets (k_rates maps consecutive items to one XCD), within a 1 GiB partial buffer
+    qchunk = std::min(qchunk, 16);
+    while (qchunk < ctx->N &&
+           (size_t)nt * (size_t)((ctx->N + qchunk - 1) / qchunk) * 3 * nT * sizeof(double) > ((size_t)1 << 30))
+      qchunk *= 2;
   }
   if (qchunk > ctx->N) qchunk = ctx->N;
   const int nchunk = (ctx->N + qchunk - 1) / qchunk;
@@ -278,6 +287,7 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
   a.inv_occ = (const double *)ctx->d_iocc.p;
   a.qchunk = qchunk;
   a.nchunk = nchunk;
+  a.nxcd = kXcds;
   a.U = ctx->d_U.p;
   a.partial = (double *)ctx->d_partial.p;
   a.pcount = (unsigned long long *)ctx->d_pcount.p;
@@ -1126,6 +1136,7 @@ int prepare_instance(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t 
   a.t0 = 0;
   a.qchunk = qchunk;
   a.nchunk = nchunk;
+  a.nxcd = kXcds;
   a.U = ctx->d_U.p;
   a.partial = (double *)ctx->d_partial.p;
   a.pcount = (unsigned long long *)ctx->d_pcount.p;

@@ -59,6 +59,7 @@ struct RateArgs {
   int t0;                   // index of the first target of the batch in the output
   int qchunk;               // q' points per work-group
   int nchunk;               // ceil(N / qchunk)
+  int nxcd;                 // XCDs the work-groups are dealt to (blockIdx round-robin)
   const void *U;            // [nt][nc][27] complex (R) precontraction of the batch
   double *partial;          // [nt_total][nchunk][3][nT]
   unsigned long long *pcount; // [nt_total][nchunk][3]

@@ -576,7 +576,15 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
 template <typename R, int NB, int NT>
 __global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int t = blockIdx.x / a.nchunk, chunk = blockIdx.x - t * a.nchunk;
+  // Work-groups reach the XCDs round-robin by blockIdx.  Remap so that XCD x walks the
+  // contiguous range x*q + min(x, rem) ... of the target-major item list: the work-groups
+  // resident on one XCD then share a few targets, whose precontraction U (re-read for every
+  // lambda') stays in that XCD's L2.
+  const unsigned nx = (unsigned)a.nxcd, b = blockIdx.x;
+  const unsigned q = gridDim.x / nx, rem = gridDim.x - q * nx;
+  const unsigned x = b % nx;
+  const unsigned item = x * q + min(x, rem) + b / nx;
+  const int t = (int)(item / (unsigned)a.nchunk), chunk = (int)(item - (unsigned)t * a.nchunk);
   rate_body<R, NB, NT>(c, a, t, chunk, smem);
 }
 
