@@ -17,6 +17,9 @@ fallback rate and the speedup over the plain FP64 kernel.
 wurtzite-like 8x8x6 grid and a 4-atom layered 6x6x6 grid at T = 300, 700 K in one
 persistent graph-captured launch with the FP32 contraction and autotuned q' chunks, timed
 against separate calls, with every rate compared to the FP64 path.
+
+``--large`` runs the 16x16x16 workload (24 576 modes) on a random subset of 512 target modes
+in FP64 and with the FP32 contraction.
 """
 from __future__ import annotations
 
@@ -222,6 +225,57 @@ def batched_main(args):
         c.close()
 
 
+def large_main(args):
+    """16x16x16 grid (24 576 modes), second-shell FC4, T = 300 K: a seeded random subset of
+    512 target modes in FP64 and with the FP32 contraction, every rate of the FP32 path
+    compared with the FP64 path; the full-grid time is extrapolated from the subset."""
+    import synth
+    import paper_2104_04895_amd as fp4
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    inst = synth.large()
+    ctx = fp4.Context(0)
+    ctx.load_instance(inst)
+    ctx.set_param(fp4.FP4_PARAM_PROFILE, 1)
+    rng = np.random.default_rng(1003)
+    act = np.flatnonzero(inst.omega.reshape(-1) > 0)
+    targets = np.sort(rng.choice(act, size=args.subset, replace=False)).astype(np.int32)
+    log(f"16^3 workload: {inst.nmodes} modes, {inst.fc4.n} quartets, subset {len(targets)}")
+    out = {}
+    r64 = None
+    for name, prec in (("fp64", fp4.FP4_FP64), ("fp32", fp4.FP4_FP32)):
+        t0 = time.perf_counter()
+        r, _, cnt = ctx.compute_rates4(inst.T, 1.0, 7, prec, targets)
+        wall = time.perf_counter() - t0
+        tm = ctx.last_timing()
+        out[name] = {"wall_s": wall, "kernel_ms": tm["ms_main"], "processes": int(cnt.sum()),
+                     "processes_per_s": int(cnt.sum()) / (tm["ms_main"] / 1e3)}
+        if r64 is None:
+            r64 = r
+        else:
+            rel = np.abs(r - r64) / np.maximum(np.abs(r64), 1e-300)
+            rel[r64 == 0] = 0.0
+            out[name]["max_rel_err_vs_fp64_path"] = float(rel.max())
+            out[name]["median_rel_err_vs_fp64_path"] = float(np.median(rel[r64 > 0]))
+        log(f"{name}: {wall:.1f} s, kernel {tm['ms_main']:.0f} ms, {int(cnt.sum())} processes")
+    full = out["fp64"]["kernel_ms"] / 1e3 * len(act) / len(targets)
+    res = {
+        "metric": "4ph processes/sec and rates time-to-solution; FP64 vs mixed at stated rel. err",
+        "value": out["fp64"]["processes_per_s"], "unit": "processes/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"diamond-structure 2-atom cell, 16x16x16 grid (24576 modes), "
+                               f"second-shell FC4, T=300 K, sb 1, random subset of {len(targets)} "
+                               f"target modes (seed 1003)"},
+        "paths": out,
+        "full_grid_fp64_seconds_extrapolated": full,
+        "fp32_speedup": out["fp64"]["kernel_ms"] / out["fp32"]["kernel_ms"],
+    }
+    print(json.dumps(res))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +288,9 @@ def main():
                     help="before the steps, run one elementwise pass that reads and writes "
                          "256 MiB (calibrates hardware traffic counters)")
     ap.add_argument("--surrogate", action="store_true", help="run the learned-surrogate workload")
+    ap.add_argument("--large", action="store_true",
+                    help="16x16x16 workload on a random subset of target modes, FP64 and FP32")
+    ap.add_argument("--subset", type=int, default=512)
     ap.add_argument("--batched", action="store_true",
                     help="run the batched uneven-instance workload (one graph-captured launch)")
     ap.add_argument("--train-grid", type=int, default=12)
@@ -254,6 +311,9 @@ def main():
         return
     if args.batched:
         batched_main(args)
+        return
+    if args.large:
+        large_main(args)
         return
 
     import torch

@@ -291,14 +291,14 @@ __device__ __forceinline__ unsigned row_bits(const Crystal &c, const RateArgs &a
   unsigned bits = 0u;
   if (orient == 0) {
     const double bw = add_signed(aw, vr.w, S2);
-#pragma unroll 2
+#pragma unroll
     for (int cc = 0; cc < NB; ++cc) {
       const double4 vc = c.mode4[iqc * NB + cc];
       double dw, s2;
       if (vc.w > 0.0 && window_keep(bw, vc.w, vr, vc, a.c_win, dw, s2)) bits |= 1u << cc;
     }
   } else {
-#pragma unroll 2
+#pragma unroll
     for (int cc = 0; cc < NB; ++cc) {
       const double4 vc = c.mode4[iqc * NB + cc];
       double dw, s2;
@@ -355,9 +355,13 @@ __device__ __forceinline__ void gamma_row(const Crystal &c, const RateArgs &a,
     const double sig2 = a.c_sig * s2;
     double delta = 1.0;
     if (!(sig2 < a.c_min)) {
-      // adaptive Gaussian, 1/sqrt(pi) = 0.5641895835477563
-      const double is2 = 1.0 / sig2;
-      delta = exp(-(dw * dw) * is2) * (0.5641895835477563 * sqrt(is2));
+      // adaptive Gaussian exp(-dw^2/sigma^2) / (sqrt(pi) sigma), 1/sqrt(pi) =
+      // 0.5641895835477563; y = 1/sigma from the hardware reciprocal square root refined
+      // by two Newton steps (relative error at the FP64 rounding level)
+      double y = __builtin_amdgcn_rsq(sig2);
+      y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
+      y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
+      delta = exp(-(dw * dw) * (y * y)) * (0.5641895835477563 * y);
     }
     const double base = kw * p2.iw * p3.iw * v2abs * delta;
 #pragma unroll
