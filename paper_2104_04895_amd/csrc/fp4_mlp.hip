@@ -1,5 +1,6 @@
 // fp4_mlp.hip -- small multilayer perceptron for the learned rate surrogate: FP32 training
-// (forward, backward, Adam) and BF16 inference, all in hand-written kernels.
+// (forward, backward, Adam) and BF16 inference on the matrix cores, all in hand-written
+// kernels.
 //
 // Network: nin -> width (SiLU) -> ... -> width (SiLU) -> 2, with `depth` linear layers in
 // total.  Output 0 is the predicted log rate mu, output 1 the predicted log standard
@@ -133,32 +134,77 @@ __global__ void k_gather(const float *X, const float *Y, const int *idx, int M, 
   Yb[i] = Y[r];
 }
 
-// round-to-nearest-even FP32 -> BF16 -> FP32
-__device__ __forceinline__ float bf16r(float x) {
+// ---------------------------------------------------------------- BF16 inference on MFMA
+//
+// Inputs and weights are stored as BF16 (round to nearest even), products accumulate in
+// FP32 on the matrix cores (v_mfma_f32_16x16x16_bf16), bias and SiLU are applied in FP32 and
+// hidden activations are rounded to BF16 for the next layer.  Operand layouts of the 16x16x16
+// instruction (lane l, element e of the 4-wide register): A[i][k] with i = l % 16,
+// k = 4 (l / 16) + e; B[k][j] with j = l % 16, k = 4 (l / 16) + e; D[i][j] with j = l % 16,
+// i = 4 (l / 16) + e.
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16bits(float x) {
   unsigned u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return x;
   u += 0x7fffu + ((u >> 16) & 1u);
-  return __uint_as_float(u & 0xffff0000u);
+  return (unsigned short)(u >> 16);
 }
 
-__global__ void k_to_bf16(const float *a, float *b, long n) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = bf16r(a[i]);
-}
-
-// BF16 inference layer: inputs and weights are BF16 values (held in FP32 registers), products
-// accumulate in FP32, outputs are rounded to BF16 after the activation.  One thread per
-// output element.
-__global__ void k_fwd_bf16(int M, int N, int K, const float *X, const float *W, const float *b,
-                           float *H, int act) {
+// dst[r][c] (rows_pad x cols_pad) = bf16(src[r * lds + c]) inside rows x cols, 0 outside
+__global__ void k_pack_bf16(const float *src, int rows, int cols, long lds, unsigned short *dst,
+                            int rows_pad, int cols_pad) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)M * N) return;
-  const int i = (int)(e / N), j = (int)(e % N);
-  float acc = 0.f;
-  for (int k = 0; k < K; ++k) acc = fmaf(X[(long)i * K + k], W[(long)j * K + k], acc);
-  float v = acc + b[j];
-  if (act) v = v / (1.f + expf(-v));
-  H[e] = act ? bf16r(v) : v;
+  if (e >= (long)rows_pad * cols_pad) return;
+  const int r = (int)(e / cols_pad), c = (int)(e % cols_pad);
+  dst[e] = (r < rows && c < cols) ? bf16bits(src[(long)r * lds + c]) : (unsigned short)0;
+}
+
+// One layer: X [Mp][Kp] BF16 (Mp a multiple of 64, Kp of 16, zero padded), W [Np][Kp] BF16
+// (Np a multiple of 16, zero padded), bias [N].  Work-group: 4 wavefronts x 16 rows, the
+// 128-column group blockIdx.y.  Hidden layers write Hb [Mp][Np] BF16 (the next layer's
+// input), the last layer Hf [M][N] FP32.
+__global__ __launch_bounds__(256) void k_fwd_mfma(int M, int Kp, int N, int Np,
+                                                  const unsigned short *__restrict__ X,
+                                                  const unsigned short *__restrict__ W,
+                                                  const float *__restrict__ bias,
+                                                  unsigned short *Hb, float *Hf, int act) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.x * 64 + wave * 16;
+  const int nt0 = blockIdx.y * 8;
+  const int ntiles = min(8, Np / 16 - nt0);
+  const int i = lane & 15, kq = lane >> 4;
+  v4f32 acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
+  const unsigned short *xa = X + (long)(m0 + i) * Kp + 4 * kq;
+  for (int k0 = 0; k0 < Kp; k0 += 16) {
+    const v4i16 a = *reinterpret_cast<const v4i16 *>(xa + k0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (t < ntiles) {
+        const v4i16 b = *reinterpret_cast<const v4i16 *>(W + (long)((nt0 + t) * 16 + i) * Kp + 4 * kq + k0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if (t >= ntiles) continue;
+    const int col = (nt0 + t) * 16 + i;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = m0 + 4 * kq + e;
+      if (col >= N) continue;
+      float v = acc[t][e] + bias[col];
+      if (act) {
+        v = v / (1.f + expf(-v));
+        Hb[(long)row * Np + col] = bf16bits(v);
+      } else if (row < M) {
+        Hf[(long)row * N + col] = v;
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -170,7 +216,7 @@ struct fp4_mlp {
   std::vector<int> in_dim, out_dim;
   std::vector<size_t> w_off, b_off;
   size_t nparam = 0;
-  float *d_p = nullptr, *d_g = nullptr, *d_m = nullptr, *d_v = nullptr, *d_pb = nullptr;
+  float *d_p = nullptr, *d_g = nullptr, *d_m = nullptr, *d_v = nullptr;
   long adam_t = 0;
   std::string err;
   int fail(int code, const std::string &m) {
@@ -228,6 +274,55 @@ int alloc_work(fp4_mlp *m, Work &w, size_t M) {
   MLP_HIP(m, hipMalloc(&w.loss, sizeof(float) * M));
   MLP_HIP(m, hipMalloc(&w.y, sizeof(float) * M));
   return FP4_OK;
+}
+
+// BF16 forward pass on MFMA from w.H[0] (M rows, FP32) into w.H[depth] (FP32 [M][2]).
+int forward_bf16_mfma(fp4_mlp *m, Work &w, int M) {
+  const int Mp = (M + 63) / 64 * 64;
+  auto pad16 = [](int v) { return (v + 15) / 16 * 16; };
+  int maxk = pad16(m->nin);
+  for (int l = 0; l < m->depth; ++l) maxk = std::max(maxk, pad16(m->out_dim[l]));
+  unsigned short *act[2] = {nullptr, nullptr}, *wb = nullptr;
+  size_t wtot = 0;
+  for (int l = 0; l < m->depth; ++l) wtot += (size_t)pad16(m->out_dim[l]) * pad16(m->in_dim[l]);
+  hipError_t e = hipMalloc(&act[0], sizeof(unsigned short) * (size_t)Mp * maxk);
+  if (e == hipSuccess) e = hipMalloc(&act[1], sizeof(unsigned short) * (size_t)Mp * maxk);
+  if (e == hipSuccess) e = hipMalloc(&wb, sizeof(unsigned short) * wtot);
+  int rc = FP4_OK;
+  if (e != hipSuccess) rc = m->fail(FP4_E_NOMEM, std::string("BF16 work buffers: ") + hipGetErrorString(e));
+  if (!rc) {
+    // zero-padded BF16 copies of the input rows and of every weight matrix
+    const int k0 = pad16(m->nin);
+    hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)(((long)Mp * k0 + 255) / 256)), dim3(256), 0,
+                       m->stream, w.H[0], M, m->nin, (long)m->nin, act[0], Mp, k0);
+    size_t off = 0;
+    std::vector<size_t> woff(m->depth);
+    for (int l = 0; l < m->depth && !rc; ++l) {
+      const int np = pad16(m->out_dim[l]), kp = pad16(m->in_dim[l]);
+      woff[l] = off;
+      hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)(((long)np * kp + 255) / 256)), dim3(256), 0,
+                         m->stream, m->d_p + m->w_off[l], m->out_dim[l], m->in_dim[l],
+                         (long)m->in_dim[l], wb + off, np, kp);
+      off += (size_t)np * kp;
+    }
+    for (int l = 0; l < m->depth && !rc; ++l) {
+      const int np = pad16(m->out_dim[l]), kp = pad16(m->in_dim[l]);
+      const int last = l + 1 == m->depth;
+      dim3 grid((unsigned)(Mp / 64), (unsigned)((np / 16 + 7) / 8));
+      hipLaunchKernelGGL(k_fwd_mfma, grid, dim3(256), 0, m->stream, M, kp, m->out_dim[l], np,
+                         act[l & 1], wb + woff[l], m->d_p + m->b_off[l], act[(l + 1) & 1],
+                         w.H[m->depth], last ? 0 : 1);
+    }
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) rc = m->fail(FP4_E_DEVICE, hipGetErrorString(le));
+    // the buffers are freed after the stream has finished with them
+    const hipError_t se = hipStreamSynchronize(m->stream);
+    if (!rc && se != hipSuccess) rc = m->fail(FP4_E_DEVICE, hipGetErrorString(se));
+  }
+  (void)hipFree(act[0]);
+  (void)hipFree(act[1]);
+  (void)hipFree(wb);
+  return rc;
 }
 
 // forward pass from w.H[0] (M rows); FP32 parameters p
@@ -316,7 +411,6 @@ int fp4_mlp_create(fp4_mlp **out, int device_id, int32_t nin, int32_t width, int
   if (e == hipSuccess) e = hipMalloc(&m->d_g, off * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&m->d_m, off * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&m->d_v, off * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&m->d_pb, off * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(m->d_p, p.data(), off * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(m->d_m, 0, off * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_v, 0, off * sizeof(float));
@@ -335,7 +429,6 @@ void fp4_mlp_destroy(fp4_mlp *m) {
   (void)hipFree(m->d_g);
   (void)hipFree(m->d_m);
   (void)hipFree(m->d_v);
-  (void)hipFree(m->d_pb);
   if (m->stream) (void)hipStreamDestroy(m->stream);
   delete m;
 }
@@ -460,17 +553,7 @@ int fp4_mlp_predict(fp4_mlp *m, const float *X, int32_t n, int32_t bf16, float *
   }
   if (!rc) {
     if (bf16) {
-      const long np = (long)m->nparam, nx = (long)n * m->nin;
-      hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, m->stream, m->d_p, m->d_pb, np);
-      hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, m->stream, w.H[0], w.H[0], nx);
-      for (int l = 0; l < m->depth && !rc; ++l) {
-        const long tot = (long)n * m->out_dim[l];
-        hipLaunchKernelGGL(k_fwd_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, m->stream, n,
-                           m->out_dim[l], m->in_dim[l], w.H[l], m->d_pb + m->w_off[l],
-                           m->d_pb + m->b_off[l], w.H[l + 1], (int)(l + 1 < m->depth));
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) rc = m->fail(FP4_E_DEVICE, hipGetErrorString(e));
-      }
+      rc = forward_bf16_mfma(m, w, n);
     } else {
       rc = forward(m, w, n, m->d_p);
     }

@@ -67,3 +67,34 @@ def test_gpu_training_and_bf16_inference(fp4):
         out16, _ = net.predict(X, bf16=True)
     assert np.sqrt(np.mean((out32[:, 0] - y) ** 2)) < 0.05
     assert np.max(np.abs(out16[:, 0] - out32[:, 0])) < 0.05
+
+
+def _bf16(x):
+    """Round to nearest even BF16 (as float64)."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.gpu
+def test_gpu_bf16_mfma_inference_against_bf16_reference(fp4):
+    """BF16 inference on the matrix cores against a host evaluation with the same roundings
+    (BF16 inputs, weights and hidden activations, wide accumulation): the MFMA operand
+    layouts, the zero padding of K = 18 and of the 2-wide output layer, and a ragged row
+    count (1000 rows, not a multiple of 64) are all exercised."""
+    rng = np.random.default_rng(4)
+    nin, width, depth = 18, 128, 5
+    X = rng.standard_normal((1000, nin)).astype(np.float32)
+    with fp4.Mlp(0, nin, width, depth, seed=11) as net:
+        p = net.get_params().astype(np.float64)
+        out, _ = net.predict(X, bf16=True)
+    dims, _ = mlp_ref.layout(nin, width, depth)
+    h = _bf16(X)
+    for l, (i, o, wo, bo) in enumerate(dims):
+        W = _bf16(p[wo:wo + i * o].reshape(o, i).astype(np.float32))
+        z = h @ W.T + p[bo:bo + o]
+        h = _bf16(z / (1.0 + np.exp(-z))) if l + 1 < depth else z
+    err = np.abs(out - h)
+    scale = np.max(np.abs(h))
+    assert np.median(err) <= 1e-3 * scale
+    assert np.max(err) <= 3e-2 * scale
