@@ -33,6 +33,20 @@ template <> __device__ __forceinline__ const float2 *PHDtab<float>(const Crystal
 __device__ __forceinline__ void pin(double2 &v) { __asm__ volatile("" : "+v"(v.x), "+v"(v.y)::"memory"); }
 __device__ __forceinline__ void pin(float2 &v) { __asm__ volatile("" : "+v"(v.x), "+v"(v.y)::"memory"); }
 
+// q = x / g, r = x % g for 0 <= x < 2^24 and 1 <= g: a single-precision estimate of the
+// quotient (off by at most one since x is exact in FP32) corrected by one integer step.
+__device__ __forceinline__ void divmod_small(int x, int g, float inv_g, int &q, int &r) {
+  q = (int)((float)x * inv_g);
+  r = x - q * g;
+  if (r < 0) {
+    q -= 1;
+    r += g;
+  } else if (r >= g) {
+    q += 1;
+    r -= g;
+  }
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -276,12 +290,12 @@ struct Acc {
 // applied with a relative margin of 1e-6, far above FP64 rounding, so it never drops a
 // process the exact test would keep.
 template <int NB, int S2>
-__device__ __forceinline__ unsigned row_bits(const Crystal &c, const RateArgs &a, double aw,
-                                             int mur, int iqc, int orient) {
-  const double4 vr = c.mode4[mur];
+__device__ __forceinline__ unsigned row_bits_pre(const Crystal &c, const RateArgs &a, double aw,
+                                                 const double4 vr, const double4 qb, int iqc,
+                                                 int orient) {
   if (!(vr.w > 0.0)) return 0u;
   {
-    const double4 qb = c.qbound[iqc];   // (w_min, w_max, v_max, sqrt(0)) over active branches
+    // qb = (w_min, w_max, v_max, 0) over the active branches of the column point
     const double x = orient == 0 ? add_signed(aw, vr.w, S2) : aw - vr.w;
     const double lo = x - qb.y, hi = x - qb.x;
     const double dist = lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0);
@@ -307,6 +321,12 @@ __device__ __forceinline__ unsigned row_bits(const Crystal &c, const RateArgs &a
     }
   }
   return bits;
+}
+
+template <int NB, int S2>
+__device__ __forceinline__ unsigned row_bits(const Crystal &c, const RateArgs &a, double aw,
+                                             int mur, int iqc, int orient) {
+  return row_bits_pre<NB, S2>(c, a, aw, c.mode4[mur], c.qbound[iqc], iqc, orient);
 }
 
 // What Gamma needs of a mode besides V: (v, w), 1/w and n0 at each temperature.
@@ -409,37 +429,63 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   // weight of the channel (Eq. tao0), prefactor C4/N^2 and 1/(w w') of Eq. 4phgamma
   const double kw = WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
   const unsigned long long lt = (1ull << lane) - 1ull;
-  auto fold3 = [&](int iq2) {
-    const int4 nq2 = c.qn[iq2];
-    const int x = wrap(nq.x + S1 * nq1.x + S2 * nq2.x, c.g0);
-    const int y = wrap(nq.y + S1 * nq1.y + S2 * nq2.y, c.g1);
-    const int z = wrap(nq.z + S1 * nq1.z + S2 * nq2.z, c.g2);
-    return x + c.g0 * (y + c.g1 * z);
-  };
   // q'' is dealt to the wavefronts in rounds of GPW consecutive points, so that every
   // wavefront sees the whole range (the mirror-pair members are not spread evenly over it)
   const int nk = (c.N + 4 * GPW - 1) / (4 * GPW);
   constexpr int KSEG = QSEG / GPW;
+  // the column point is fold(b3 + s'' q''), b3 = q + s' q'; DK = grid digits of the
+  // per-round step 4 GPW of q''
+  const int4 b3 = make_int4(nq.x + S1 * nq1.x, nq.y + S1 * nq1.y, nq.z + S1 * nq1.z, 0);
+  const int4 DK = make_int4((4 * GPW) % c.g0, ((4 * GPW) / c.g0) % c.g1, (4 * GPW) / (c.g0 * c.g1), 0);
+  auto fold_d = [&](int4 n2) {
+    const int x = wrap(b3.x + S2 * n2.x, c.g0);
+    const int y = wrap(b3.y + S2 * n2.y, c.g1);
+    const int z = wrap(b3.z + S2 * n2.z, c.g2);
+    return x + c.g0 * (y + c.g1 * z);
+  };
+  const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
   for (int k0 = 0; k0 < nk; k0 += KSEG) {
     const int k1 = min(nk, k0 + KSEG);
-    // phase 1: queue
+    // phase 1: queue.  The grid digits of q'' advance arithmetically by DK per round (no
+    // index-table load), and the row and bound records of the next round are fetched
+    // while the current round is tested.
     int cnt = 0;
+    int iq2 = (k0 * 4 + wave) * GPW + gw;
+    int4 d2 = c.qn[min(iq2, c.N - 1)];
+    int iq3 = fold_d(d2);
+    const bool live0 = !MIRROR && glane && iq2 < c.N;
+    double4 vr = live0 ? c.mode4[iq2 * NB + r] : make_double4(0.0, 0.0, 0.0, 0.0);
+    double4 qb = live0 ? c.qbound[iq3] : make_double4(0.0, 0.0, 0.0, 0.0);
     for (int k = k0; k < k1; ++k) {
-      const int iq2 = (k * 4 + wave) * GPW + gw;
+      const int iq2c = iq2, iq3c = iq3;
+      const double4 vrc = vr, qbc = qb;
+      // next round
+      iq2 += 4 * GPW;
+      d2.x += DK.x;
+      const int cx = d2.x >= c.g0;
+      d2.x -= cx ? c.g0 : 0;
+      d2.y += DK.y + cx;
+      const int cy = d2.y >= c.g1;
+      d2.y -= cy ? c.g1 : 0;
+      d2.z += DK.z + cy;
+      iq3 = fold_d(d2);
+      if (!MIRROR && glane && k + 1 < k1 && iq2 < c.N) {
+        vr = c.mode4[iq2 * NB + r];
+        qb = c.qbound[iq3];
+      }
       bool keep = false;
-      if (glane && iq2 < c.N) {
-        const int iq3 = fold3(iq2);
+      if (glane && iq2c < c.N) {
         if (MIRROR) {
-          keep = iq2 <= iq3;
+          keep = iq2c <= iq3c;
         } else {
-          const unsigned bits = row_bits<NB, S2>(c, a, aw, iq2 * NB + r, iq3, 0);
+          const unsigned bits = row_bits_pre<NB, S2>(c, a, aw, vrc, qbc, iq3c, 0);
           const unsigned long long bal = __ballot(bits != 0u);
           keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
         }
       }
       const bool lead = keep && r == 0;
       const unsigned long long lb = __ballot(lead);
-      if (lead) Qw[cnt + __popcll(lb & lt)] = iq2;
+      if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
       cnt += __popcll(lb);
     }
     wave_sync();
@@ -447,7 +493,14 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
     if (glane) {
       for (int e = gw; e < cnt; e += GPW) {
         const int iq2 = Qw[e];
-        const int iq3 = fold3(iq2);
+        // grid digits of q'' by division (no index-table load on the critical path)
+        int4 n2;
+        {
+          int t;
+          divmod_small(iq2, c.g0, inv_g0, t, n2.x);
+          divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
+        }
+        const int iq3 = fold_d(n2);
         const int mur = iq2 * NB + r;
         const unsigned bA = row_bits<NB, S2>(c, a, aw, mur, iq3, 0);
         const unsigned bB = (MIRROR && iq2 != iq3) ? row_bits<NB, S2>(c, a, aw, mur, iq3, 1) : 0u;
