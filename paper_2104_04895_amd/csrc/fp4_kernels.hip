@@ -200,6 +200,11 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
   using CR = typename CT<R>::T;
   constexpr int NAT = NB / 3;
   const int k = r / 3, gam = r - 3 * k;
+  // the row of E3 is fetched first, so that its latency overlaps the phase staging and F
+  const CR *e3 = Etab<R>(c) + ((size_t)iq2 * NB + r) * NB;
+  CR e3v[NB];
+#pragma unroll
+  for (int kg = 0; kg < NB; ++kg) e3v[kg] = e3[kg];
   // stage exp(i s'' q''.d) of every distinct d in the group's phase tile
   {
     const CR *phd = PHDtab<R>(c) + (size_t)iq2 * c.nd;
@@ -239,14 +244,21 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
     }
   }
   wave_sync();
-  // H = E3[r][:] F
-  const CR *e3 = Etab<R>(c) + ((size_t)iq2 * NB + r) * NB;
+  // the row of E4 (lane r: conj(E[q'''][r][:])) is fetched before H = E3[r][:] F when the
+  // registers allow it (FP32)
+  const CR *e4 = Etab<R>(c) + ((size_t)iq3 * NB + r) * NB;
+  constexpr bool PRE4 = sizeof(R) == 4;
+  CR e4v[NB];
+  if (PRE4) {
+#pragma unroll
+    for (int col = 0; col < NB; ++col) e4v[col] = e4[col];
+  }
   CR H[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) H[i] = czero<CR>();
 #pragma unroll
   for (int kg = 0; kg < NB; ++kg) {
-    CR e = e3[kg];
+    CR e = e3v[kg];
     if (S2 < 0) e = cconj(e);
 #pragma unroll
     for (int col = 0; col < NB; ++col) cmac(H[col], e, Xg[kg * NB + col]);
@@ -254,10 +266,8 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
     for (int col = 0; col < NB; ++col) pin(H[col]);
   }
   wave_sync();
-  // E4 rows: lane r writes row r = conj(E[q'''][r][:])
-  const CR *e4 = Etab<R>(c) + ((size_t)iq3 * NB + r) * NB;
 #pragma unroll
-  for (int col = 0; col < NB; ++col) Xg[r * NB + col] = cconj(e4[col]);
+  for (int col = 0; col < NB; ++col) Xg[r * NB + col] = cconj(PRE4 ? e4v[col] : e4[col]);
   wave_sync();
 #pragma unroll
   for (int cc = 0; cc < NB; ++cc) {
