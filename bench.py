@@ -53,7 +53,7 @@ def kernel_sources_hash():
 
 
 def algorithmic_flops(stats, inst, n_pairs):
-    """Algorithmic FLOPs of one main-kernel launch (per-unit figures in the design doc):
+    """Algorithmic FLOPs of one main-kernel launch, the cheapest grouping of the arithmetic:
     W'' build 456 per combo per (lambda, lambda') pair, branch block 72 ng + 16 nb^3 per
     contracted block, Gamma 40 + 6 nT per kept process (the per-candidate window test is
     not credited)."""
