@@ -357,30 +357,50 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
   return r;
 }
 
-// Gamma (Eq. 4phgamma) of the kept processes of one row and orientation, accumulated into
-// the lane's FP64 partial rates.  Vrow[cc] is V of the row's process with column cc; rrec
-// is the row mode's record.  The record of the next kept column is fetched while the
+// Gamma (Eq. 4phgamma) of a compacted list of kept processes of the wavefront's blocks,
+// accumulated into the lane's FP64 partial rates.  Entry i of L is (s << 5) | b for the
+// process of source lane s = (group g, row r) and kept bit b: b < NB is the process
+// (lambda'' = (q''_g, r), lambda''' = (q'''_g, b)), b >= NB the mirrored one
+// (lambda'' = (q'''_g, b - NB), lambda''' = (q''_g, r)).  V is read from the group's tile,
+// (q''_g, q'''_g) from Gq.  Consecutive lanes take consecutive entries, so every lane has
+// work while the list lasts; the records of the lane's next entry are fetched while the
 // current one is evaluated.
 template <typename R, int NB, int NT, int CH>
-__device__ __forceinline__ void gamma_row(const Crystal &c, const RateArgs &a,
-                                          const typename CT<R>::T *Vrow, unsigned bits,
-                                          int orient, const ModeRec<NT> &rrec, int iqc,
-                                          double aw, double kw, const double (&invn)[NT],
-                                          const double (&n1)[NT], Acc<NT> &acc) {
+__device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
+                                           const unsigned short *L, int cnt, int lane,
+                                           const typename CT<R>::T *Xw, const int2 *Gq,
+                                           double aw, double kw, const double (&invn)[NT],
+                                           const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
   constexpr int S2 = (CH == 0) ? 1 : -1;
-  ModeRec<NT> nx = load_rec<NB, NT>(c, a, iqc * NB + __builtin_ctz(bits));
+  auto decode = [&](int i, int &mu2, int &mu3, int &vi) {
+    const unsigned d = L[i];
+    const int s = (int)(d >> 5), b = (int)(d & 31u);
+    const int g = s / NB, r = s - g * NB;
+    const int2 q = Gq[g];
+    const int cc = b >= NB ? b - NB : b;
+    const int mr = q.x * NB + r, mc = q.y * NB + cc;
+    mu2 = b >= NB ? mc : mr;
+    mu3 = b >= NB ? mr : mc;
+    vi = g * NB * NB + r * NB + cc;
+  };
+  int i = lane;
+  if (i >= cnt) return;
+  int mu2n, mu3n, vin;
+  decode(i, mu2n, mu3n, vin);
+  ModeRec<NT> p2n = load_rec<NB, NT>(c, a, mu2n), p3n = load_rec<NB, NT>(c, a, mu3n);
 #pragma unroll 1
-  while (bits) {
-    const int cc = __builtin_ctz(bits);
-    bits &= bits - 1u;
-    const ModeRec<NT> col = nx;
-    if (bits) nx = load_rec<NB, NT>(c, a, iqc * NB + __builtin_ctz(bits));
-    const ModeRec<NT> &p2 = orient == 0 ? rrec : col;
-    const ModeRec<NT> &p3 = orient == 0 ? col : rrec;
+  for (; i < cnt; i += 64) {
+    const ModeRec<NT> p2 = p2n, p3 = p3n;
+    const int vi = vin;
+    if (i + 64 < cnt) {
+      decode(i + 64, mu2n, mu3n, vin);
+      p2n = load_rec<NB, NT>(c, a, mu2n);
+      p3n = load_rec<NB, NT>(c, a, mu3n);
+    }
     double dw, s2;
     window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
-    const CR vv = Vrow[cc];
+    const CR vv = Xw[vi];
     const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
     const double sig2 = a.c_sig * s2;
     double delta = 1.0;
@@ -410,7 +430,8 @@ __device__ __forceinline__ void gamma_row(const Crystal &c, const RateArgs &a,
   }
 }
 
-constexpr int QSEG = 512;   // q'' points a wavefront queues at a time
+constexpr int QSEG = 256;   // q'' points a wavefront queues at a time
+constexpr int LSEG = 256;   // kept processes a wavefront evaluates per pass
 
 // All blocks (q'') of one channel for fixed lambda, lambda'.  Each wavefront owns a quarter
 // of the q'' points.  Phase 1 compacts the blocks worth contracting into the wavefront's LDS
@@ -424,8 +445,10 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
                                                int gw, int r, bool glane,
                                                typename CT<R>::T *Xg, typename CT<R>::T *Pg,
                                                const int *sg_d, const int *skl, int *Qw,
-                                               int4 nq, int4 nq1, int mu, int mu1, double w,
-                                               double w1, const double (&invn)[NT],
+                                               const typename CT<R>::T *Xw, int2 *Gq,
+                                               unsigned short *Lw, int4 nq, int4 nq1, int mu,
+                                               int mu1, double w, double w1,
+                                               const double (&invn)[NT],
                                                const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
   constexpr int GPW = 64 / NB;
@@ -499,10 +522,15 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       cnt += __popcll(lb);
     }
     wave_sync();
-    // phase 2: contract the queued blocks
-    if (glane) {
-      for (int e = gw; e < cnt; e += GPW) {
-        const int iq2 = Qw[e];
+    // phase 2: contract the queued blocks, GPW at a time (one per lane group), then
+    // evaluate their kept processes as one compacted list
+    for (int e0 = 0; e0 < cnt; e0 += GPW) {
+      const int e = e0 + gw;
+      const bool act = glane && e < cnt;
+      int iq2 = 0, iq3 = 0;
+      unsigned bA = 0u, bB = 0u;
+      if (act) {
+        iq2 = Qw[e];
         // grid digits of q'' by division (no index-table load on the critical path)
         int4 n2;
         {
@@ -510,23 +538,44 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
           divmod_small(iq2, c.g0, inv_g0, t, n2.x);
           divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
         }
-        const int iq3 = fold_d(n2);
+        iq3 = fold_d(n2);
         const int mur = iq2 * NB + r;
-        const unsigned bA = row_bits<NB, S2>(c, a, aw, mur, iq3, 0);
-        const unsigned bB = (MIRROR && iq2 != iq3) ? row_bits<NB, S2>(c, a, aw, mur, iq3, 1) : 0u;
-        const unsigned long long bal = __ballot((bA | bB) != 0u);
-        if (((bal >> (gw * NB)) & GMASK) == 0ull) continue;   // nothing survives in the block
-        if (r == 0) acc.blocks += 1;
+        bA = row_bits<NB, S2>(c, a, aw, mur, iq3, 0);
+        bB = (MIRROR && iq2 != iq3) ? row_bits<NB, S2>(c, a, aw, mur, iq3, 1) : 0u;
+      }
+      const unsigned long long bal = __ballot((bA | bB) != 0u);
+      const bool blk = act && ((bal >> (gw * NB)) & GMASK) != 0ull;
+      if (blk && r == 0) acc.blocks += 1;
+      if (blk) {
         CR V[NB];
         block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
-        if ((bA | bB) == 0u) continue;
-        // the lane's row of V goes through its own row of the group tile, so that the
-        // survivor loop is not unrolled
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
-        const ModeRec<NT> rrec = load_rec<NB, NT>(c, a, mur);
-        if (bA) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bA, 0, rrec, iq3, aw, kw, invn, n1, acc);
-        if (bB) gamma_row<R, NB, NT, CH>(c, a, Xg + r * NB, bB, 1, rrec, iq3, aw, kw, invn, n1, acc);
+      }
+      if (act && r == 0) Gq[gw] = make_int2(iq2, iq3);
+      // place of the lane's kept processes in the wavefront's list: prefix sum of the
+      // per-lane counts (<= 2 NB < 32) by bit-sliced ballots
+      const unsigned m = blk ? (bA | (bB << NB)) : 0u;
+      const int n = __popc(m);
+      int pre = 0, tot = 0;
+#pragma unroll
+      for (int bsl = 0; bsl < 5; ++bsl) {
+        const unsigned long long bb = __ballot((n >> bsl) & 1);
+        pre += __popcll(bb & lt) << bsl;
+        tot += __popcll(bb) << bsl;
+      }
+      for (int base = 0; base < tot; base += LSEG) {
+        unsigned mm = m;
+        int idx = pre;
+        while (mm) {
+          const int b = __builtin_ctz(mm);
+          mm &= mm - 1u;
+          if (idx >= base && idx < base + LSEG) Lw[idx - base] = (unsigned short)((lane << 5) | b);
+          ++idx;
+        }
+        wave_sync();
+        gamma_list<R, NB, NT, CH>(c, a, Lw, min(LSEG, tot - base), lane, Xw, Gq, aw, kw, invn, n1, acc);
+        wave_sync();
       }
     }
     wave_sync();
@@ -545,9 +594,11 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
   CR *W = reinterpret_cast<CR *>(smem);                 // [2][ng][9]
   CR *X = W + 2 * c.ng * 9;                             // [NGRP][NB][NB]
   CR *P = X + NGRP * NB * NB;                           // [NGRP][nd]
-  int *sg_d = reinterpret_cast<int *>(P + NGRP * c.nd); // [ng]
+  int2 *Gq = reinterpret_cast<int2 *>(P + NGRP * c.nd); // [NGRP] current block of each group
+  int *sg_d = reinterpret_cast<int *>(Gq + NGRP);       // [ng]
   int *skl = sg_d + c.ng;                               // [nat*nat + 1]
   int *Q = skl + c.nat * c.nat + 1;                     // [4][QSEG] block queues
+  unsigned short *L = reinterpret_cast<unsigned short *>(Q + 4 * QSEG);  // [4][LSEG]
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int gw = lane / NB, r = lane - gw * NB;
@@ -556,6 +607,9 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
   CR *Xg = X + (size_t)(glane ? G : 0) * NB * NB;
   CR *Pg = P + (size_t)(glane ? G : 0) * c.nd;
   int *Qw = Q + wave * QSEG;
+  const CR *Xw = X + (size_t)wave * GPW * NB * NB;
+  int2 *Gqw = Gq + wave * GPW;
+  unsigned short *Lw = L + wave * LSEG;
   for (int i = tid; i < c.ng; i += 256) sg_d[i] = c.g_d[i];
   for (int i = tid; i <= c.nat * c.nat; i += 256) skl[i] = c.kl_start[i];
 
@@ -592,11 +646,11 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) n1[tt] = (tt < a.nT) ? a.occ[(size_t)tt * c.N * NB + mu1] : 0.0;
         if (a.mask & 1u)
-          channel_blocks<R, NB, NT, 0>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 0>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
         if (a.mask & 2u)
-          channel_blocks<R, NB, NT, 1>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 1>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
         if (a.mask & 4u)
-          channel_blocks<R, NB, NT, 2>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          channel_blocks<R, NB, NT, 2>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
       }
     }
   }
@@ -758,7 +812,9 @@ size_t rate_lds_bytes(const Crystal &c, int fp32, int NT) {
   const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
   const int NB = c.nb, GPW = 64 / NB;
   const size_t lds = cb * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB + (size_t)4 * GPW * c.nd) +
-                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1 + 4 * QSEG);
+                     sizeof(int2) * (size_t)4 * GPW +
+                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1 + 4 * QSEG) +
+                     sizeof(unsigned short) * (size_t)4 * LSEG;
   const size_t lds_red = sizeof(double) * 4 * 3 * NT + sizeof(unsigned long long) * 16;
   return lds > lds_red ? lds : lds_red;
 }
