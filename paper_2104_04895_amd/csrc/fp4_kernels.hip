@@ -224,6 +224,7 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
   for (int rl = 0; rl < NAT; ++rl) {
     const int l = (k + rl) % NAT;
     const int gb = skl[k * NAT + l], ge = skl[k * NAT + l + 1];
+#pragma unroll 2
     for (int g = gb; g < ge; ++g) {
       const CR ph = Pg[sg_d[g]];
       const CR *wg = Ws + g * 9 + gam * 3;
@@ -363,8 +364,7 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
 // (lambda'' = (q''_g, r), lambda''' = (q'''_g, b)), b >= NB the mirrored one
 // (lambda'' = (q'''_g, b - NB), lambda''' = (q''_g, r)).  V is read from the group's tile,
 // (q''_g, q'''_g) from Gq.  Consecutive lanes take consecutive entries, so every lane has
-// work while the list lasts; the records of the lane's next entry are fetched while the
-// current one is evaluated.
+// work while the list lasts.
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const unsigned short *L, int cnt, int lane,
@@ -384,20 +384,11 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
     mu3 = b >= NB ? mr : mc;
     vi = g * NB * NB + r * NB + cc;
   };
-  int i = lane;
-  if (i >= cnt) return;
-  int mu2n, mu3n, vin;
-  decode(i, mu2n, mu3n, vin);
-  ModeRec<NT> p2n = load_rec<NB, NT>(c, a, mu2n), p3n = load_rec<NB, NT>(c, a, mu3n);
 #pragma unroll 1
-  for (; i < cnt; i += 64) {
-    const ModeRec<NT> p2 = p2n, p3 = p3n;
-    const int vi = vin;
-    if (i + 64 < cnt) {
-      decode(i + 64, mu2n, mu3n, vin);
-      p2n = load_rec<NB, NT>(c, a, mu2n);
-      p3n = load_rec<NB, NT>(c, a, mu3n);
-    }
+  for (int i = lane; i < cnt; i += 64) {
+    int mu2, mu3, vi;
+    decode(i, mu2, mu3, vi);
+    const ModeRec<NT> p2 = load_rec<NB, NT>(c, a, mu2), p3 = load_rec<NB, NT>(c, a, mu3);
     double dw, s2;
     window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
     const CR vv = Xw[vi];
