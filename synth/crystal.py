@@ -123,6 +123,15 @@ def layered_rhombohedral(a_h: float = 2.82, c_h: float = 14.05,
                    [(np.eye(3), np.zeros(3))])
 
 
+def layered_three_atom(a_h: float = 2.82, c_h: float = 14.05,
+                       masses=(7.0, 56.0, 16.0), z_o: float = 0.26) -> Crystal:
+    """Three-atom cell (9 branches): the layered rhombohedral cell without its second O.
+    Only the identity is used as a symmetry operation."""
+    full = layered_rhombohedral(a_h, c_h, tuple(masses) + (16.0,), z_o)
+    return Crystal("layered_three_atom", full.A, full.tau[:3].copy(),
+                   np.array(masses, dtype=float), [(np.eye(3), np.zeros(3))])
+
+
 def check_ops(cr: Crystal, tol: float = 1e-8) -> None:
     """Assert every stored operation maps every site onto a site."""
     for T, t in cr.ops:

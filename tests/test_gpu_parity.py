@@ -236,3 +236,43 @@ def test_medium_full_size_sampled(fp4):
     r_o, _, _ = _oracle(inst, inst.T, 1.0, 7, one)
     assert _rel(r[:, one], r_o) <= RTOL64
     assert _rel(r32[:, one], r_o) <= RTOL32
+
+
+def test_three_atom_cell(fp4):
+    """Nine branches (the 3-atom instantiation of the kernels): a layered 3-atom cell on a
+    2x2x3 grid with 2001 quartets, two temperatures: counts exact and rates within 1e-10 on
+    sampled targets, FP32 within 1e-4."""
+    _say("case: three-atom cell 2x2x3")
+    from synth import configs
+    inst = configs.three_atom(grid=(2, 2, 3))
+    targets = np.arange(0, inst.nmodes, 5)
+    r_o, _, c_o = _oracle(inst, inst.T, 1.0, 7, targets)
+    with _ctx(fp4, inst) as c:
+        r, _, cnt = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64, targets)
+        r32, _, cnt32 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP32, targets)
+    assert c_o.sum() > 0
+    assert np.array_equal(cnt, c_o) and np.array_equal(cnt32, c_o)
+    assert _rel(r, r_o) <= RTOL64
+    assert _rel(r32, r_o) <= RTOL32
+
+
+def test_large_grid_properties(fp4):
+    """The 16x16x16 workload (24 576 modes, the largest benchmarked grid), where the oracle
+    is out of reach per mode: properties that hold at any size on 32 sampled q points and
+    their time-reversed partners (equal counts, rates equal to rounding), and the FP32
+    contraction within 1e-4 of FP64 with identical counts."""
+    _say("case: large 16x16x16 properties")
+    inst = synth.large()
+    rng = np.random.default_rng(9)
+    qs = rng.choice(np.arange(1, inst.nq), 32, replace=False)
+    mq = minus_index(inst.grid)
+    t1 = (qs[:, None] * inst.nb + np.arange(inst.nb)[None, :]).reshape(-1)
+    t2 = (mq[qs][:, None] * inst.nb + np.arange(inst.nb)[None, :]).reshape(-1)
+    with _ctx(fp4, inst) as c:
+        r1, _, c1 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64, t1)
+        r2, _, c2 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64, t2)
+        r32, _, c32 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP32, t1)
+    assert c1.sum() > 0
+    assert np.array_equal(c1, c2) and np.array_equal(c32, c1)
+    np.testing.assert_allclose(r2, r1, rtol=1e-12)
+    assert _rel(r32, r1) <= RTOL32

@@ -154,3 +154,15 @@ def test_rates3_argument_errors(fp4):
             c.compute_rates3([300.0], -1.0)
         r, cnt = c.compute_rates3([300.0], 1.0, targets=[5, 7])
         assert r.shape == (1, 2) and cnt.shape == (2, 2)
+
+
+def test_three_atom_cell(fp4):
+    _say("case: rates3 three-atom cell 3x3x2")
+    from synth import configs
+    inst = configs.three_atom(grid=(3, 3, 2))
+    fc3 = random_fc3(inst.cr, 2.95, np.random.default_rng(8))
+    targets = np.arange(2, inst.nmodes, 5)
+    r_o, c_o = _oracle(inst, fc3, [300.0], 1.0, targets)
+    with _ctx(fp4, inst, fc3) as c:
+        r, cnt = c.compute_rates3([300.0], 1.0, targets)
+    _check(r, cnt, r_o, c_o)
