@@ -40,15 +40,21 @@ PEAK_FP32_VALU = 157.3e12
 # HBM bytes of one FP64 k_rates launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, each scaled by the counter's reading for a plain kernel that reads and
 # writes 256 MiB; valid only for the kernel sources they were taken with.
-TRAFFIC_FP64 = {"sources_sha256_16": "558200165fe050be", "bytes": 3.640e8 + 1.975e8}
+TRAFFIC_FP64 = {"sources_sha256_16": "d53cb4438b103883", "bytes": 3.640e8 + 1.975e8}
 
 
 def kernel_sources_hash():
+    """sha256 (first 16 hex digits) of the rate kernel's sources with comments and blank
+    lines removed, so that a comment edit does not invalidate the counter readings."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("fp4_kernels.hip", "fp4_device.h", "fp4_internal.h"):
-        with open(os.path.join(ROOT, "paper_2104_04895_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2104_04895_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

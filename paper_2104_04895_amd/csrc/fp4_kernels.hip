@@ -429,7 +429,8 @@ constexpr int LSEG = 256;   // kept processes a wavefront evaluates per pass
 // queue in a fixed order (ballot + prefix count): for ++ and -- the blocks with a surviving
 // process, for +- one block of every mirror pair {q'', q'''} (V of the pair members are
 // transposes of each other).  Phase 2 lets the wavefront's lane groups contract the queued
-// blocks densely; lane r of a group owns branch row j'' = r.
+// blocks densely (lane r of a group owns branch row j'' = r) and evaluates the kept
+// processes of the blocks in flight as one compacted list.
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs &a,
                                                const typename CT<R>::T *W, int wave, int lane,
