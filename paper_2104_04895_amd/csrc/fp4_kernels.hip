@@ -687,7 +687,9 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
 }
 
 template <typename R, int NB, int NT>
-__global__ __launch_bounds__(256, 3) void k_rates(Crystal c, RateArgs a) {
+// 3 work-groups (12 wavefronts) per CU, or 4 for the FP32 contraction of up to 6 branches,
+// whose registers and LDS fit a fourth at a small spill (measured faster)
+__global__ __launch_bounds__(256, (sizeof(R) == 4 && NB <= 6) ? 4 : 3) void k_rates(Crystal c, RateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // Work-groups reach the XCDs round-robin by blockIdx.  Remap so that XCD x walks the
   // contiguous range x*q + min(x, rem) ... of the target-major item list: the work-groups
