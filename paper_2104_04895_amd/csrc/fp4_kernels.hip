@@ -709,7 +709,7 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 && NB <= 6) ? 4 : 3) void k_ra
 // instance (the host orders the instances by cost per item, most expensive first).  Crystals
 // of different branch counts run as separate persistent kernels of the same graph.
 template <typename R, int NB, int NT>
-__global__ __launch_bounds__(256, 3) void k_rates_batch(const BatchInst *__restrict__ insts, int ninst,
+__global__ __launch_bounds__(256, (sizeof(R) == 4 && NB <= 6) ? 4 : 3) void k_rates_batch(const BatchInst *__restrict__ insts, int ninst,
                                                         long long total,
                                                         unsigned long long *counter) {
   extern __shared__ __align__(16) unsigned char smem[];
