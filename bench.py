@@ -411,7 +411,16 @@ def main():
     if prec == fp4.FP4_FP64 and kernel_sources_hash() == TRAFFIC_FP64["sources_sha256_16"]:
         traffic = TRAFFIC_FP64["bytes"]
 
-    extras = {}
+    extras = {
+        "candidates_per_s": candidates / (ms_per_step / 1e3),
+        "candidates_per_step": candidates,
+        "contracted_blocks_per_step": stats["blocks"],
+        "hbm_gb_per_s": (traffic / t_main / 1e9) if traffic else None,
+    }
+    # time to solution: the synchronous call, rates and counts copied back to the host
+    t0 = time.perf_counter()
+    ctx.compute_rates4(inst.T, inst.scalebroad, inst.mask, prec)
+    extras["time_to_solution_s"] = time.perf_counter() - t0
     if not args.no_fp32 and prec == fp4.FP4_FP64:
         step(fp4.FP4_FP32)
         torch.cuda.synchronize()
