@@ -80,10 +80,15 @@ def test_small_fp32_contraction(fp4, small):
     ((2, 2, 2), synth.configs.RC_SECOND, 1.3, 5, (300.0,)),
     ((5, 1, 1), synth.configs.RC_FIRST, 1.0, 2, (300.0, 700.0)),
     ((1, 1, 1), synth.configs.RC_SECOND, 1.0, 7, (300.0,)),
+    ((3, 3, 3), synth.configs.RC_SECOND, 0.1, 7, (300.0,)),
+    ((2, 3, 2), synth.configs.RC_FIRST, 1.0, 7,
+     (100.0, 200.0, 300.0, 400.0, 600.0, 800.0, 1000.0, 1200.0)),
 ])
 def test_ragged_grids_second_shell(fp4, grid, rc, sb, mask, T):
     """Non-cubic and degenerate grids, second-shell FC4 (1522 quartets, 34 groups), several
-    temperatures and channel masks; sampled targets for the oracle."""
+    temperatures (up to the maximum of 8) and channel masks, scalebroad down to 0.1 (the
+    paper's setting, where the sigma floor fires more often); sampled targets for the
+    oracle."""
     _say("case: ragged", grid, rc, sb, mask, T)
     inst = synth.diamond_instance(grid, rc, seed=31, T=T)
     rng = np.random.default_rng(1)
