@@ -420,8 +420,3 @@ def autotune(ctx: "Context", T, scalebroad=1.0, mask=7, precision=FP4_FP64, nsam
                               int(nsample), ctypes.byref(best), _p(ms), _p(qs), 16, ctypes.byref(n)),
                "fp4_autotune")
     return best.value, {int(qs[i]): float(ms[i]) for i in range(n.value)}
-
-
-def build():
-    from .build import build as _b
-    return _b()
