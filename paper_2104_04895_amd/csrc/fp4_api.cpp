@@ -83,9 +83,14 @@ struct fp4_ctx {
   int ng = 0, nc = 0, nq4 = 0, na = 0, nbv = 0, nd = 0;
   std::vector<int> g_d, kl_start, c_start, c_jat, c_a, cq_start, q_i, q_b, avec, bvec, dvec;
   std::vector<double> q_phi;
+  // q points sorted by lowest active frequency (host copies of the uploaded tables)
+  std::vector<int> h_qord;
+  std::vector<double> h_qordw;
 
   // device buffers
   DevBuf d_omega, d_iw, d_m4, d_qbnd, d_vel, d_evec, d_mass, d_E64, d_E32, d_qn, d_PHA64, d_PHB64, d_PHD64, d_PHD32;
+  DevBuf d_qord, d_qordw;
+  double w_lo = 0.0, w_hi = 0.0, v_hi = 0.0;
   DevBuf d_g_d, d_kl, d_cs, d_cj, d_ca, d_cq, d_qi, d_qb, d_qphi, d_avec, d_bvec, d_dvec;
   DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
   DevBuf d_rates, d_rch, d_counts, d_quads, d_tslot, d_V;
@@ -173,6 +178,11 @@ fp4::Crystal make_crystal(const fp4_ctx *ctx) {
   c.vel = (const double4 *)ctx->d_vel.p;
   c.mode4 = (const double4 *)ctx->d_m4.p;
   c.qbound = (const double4 *)ctx->d_qbnd.p;
+  c.qord = (const int4 *)ctx->d_qord.p;
+  c.qord_w = (const double *)ctx->d_qordw.p;
+  c.w_lo = ctx->w_lo;
+  c.w_hi = ctx->w_hi;
+  c.v_hi = ctx->v_hi;
   c.E64 = (const double2 *)ctx->d_E64.p;
   c.E32 = (const float2 *)ctx->d_E32.p;
   c.qn = (const int4 *)ctx->d_qn.p;
@@ -215,6 +225,36 @@ int ensure_tables(fp4_ctx *ctx) {
                                   (float2 *)ctx->d_PHD32.p, (const int *)ctx->d_avec.p,
                                   (const int *)ctx->d_bvec.p, (const int *)ctx->d_dvec.p,
                                   ctx->stream));
+  // q points in ascending order of their lowest active frequency (the ++ and -- channels scan
+  // q'' in this order and stop where no row can pass the window), and the global bounds
+  {
+    std::vector<double4> qb(N);
+    FP4_HIP(ctx, hipMemcpyAsync(qb.data(), ctx->d_qbnd.p, N * sizeof(double4), hipMemcpyDeviceToHost, ctx->stream));
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<int> ord(N);
+    for (size_t i = 0; i < N; ++i) ord[i] = (int)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return qb[x].x < qb[y].x; });
+    ctx->h_qord.assign(4 * N, 0);
+    ctx->h_qordw.assign(N, 0.0);
+    double wlo = 1e300, whi = -1e300, vhi = 0.0;
+    for (size_t p = 0; p < N; ++p) {
+      const int iq = ord[p];
+      ctx->h_qord[4 * p] = iq;
+      ctx->h_qord[4 * p + 1] = iq % ctx->grid[0];
+      ctx->h_qord[4 * p + 2] = (iq / ctx->grid[0]) % ctx->grid[1];
+      ctx->h_qord[4 * p + 3] = iq / (ctx->grid[0] * ctx->grid[1]);
+      ctx->h_qordw[p] = qb[iq].x;
+      wlo = std::min(wlo, qb[iq].x);
+      whi = std::max(whi, qb[iq].y);
+      vhi = std::max(vhi, qb[iq].z);
+    }
+    ctx->w_lo = wlo;
+    ctx->w_hi = whi;
+    ctx->v_hi = vhi;
+    if ((rc = upload(ctx, ctx->d_qord, ctx->h_qord.data(), ctx->h_qord.size()))) return rc;
+    if ((rc = upload(ctx, ctx->d_qordw, ctx->h_qordw.data(), ctx->h_qordw.size()))) return rc;
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
   ctx->tables_dirty = false;
   return FP4_OK;
 }
@@ -459,7 +499,7 @@ void fp4_destroy(fp4_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_qbnd, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
+  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_qbnd, &ctx->d_qord, &ctx->d_qordw, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
                    &ctx->d_E32, &ctx->d_qn, &ctx->d_PHA64, &ctx->d_PHB64, &ctx->d_PHD64,
                    &ctx->d_PHD32, &ctx->d_g_d, &ctx->d_kl, &ctx->d_cs, &ctx->d_cj, &ctx->d_ca,
                    &ctx->d_cq, &ctx->d_qi, &ctx->d_qb, &ctx->d_qphi, &ctx->d_avec, &ctx->d_bvec,

@@ -25,6 +25,9 @@ struct Crystal {
   const double4 *vel;       // [N*nb] (x, y, z, 0)
   const double4 *mode4;     // [N*nb] (vx, vy, vz, omega)
   const double4 *qbound;    // [N] (min omega, max omega, max |v|, 0) of the active branches
+  const int4 *qord;         // [N] (iq, n1, n2, n3) of the q points in ascending qbound.x
+  const double *qord_w;     // [N] qbound.x in that order
+  double w_lo, w_hi, v_hi;  // lowest and highest active frequency, highest speed
   const double2 *E64;       // [N][nb][nb]  e_{j}(atom, x) / sqrt(M_atom), column = 3 atom + x
   const float2 *E32;        // same, FP32
   const int4 *qn;           // [N] (n1, n2, n3, 0)

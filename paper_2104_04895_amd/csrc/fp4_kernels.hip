@@ -53,6 +53,12 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Elements per group tile: an NB x NB block of V, F or E4 rows, or the NB column records
+// (4 doubles each) of the window test, whichever is larger
+__host__ __device__ constexpr int xtile(int nb, int cbytes) {
+  return nb * nb * cbytes >= 32 * nb ? nb * nb : (32 * nb) / cbytes;
+}
+
 // ------------------------------------------------------------------ table kernels
 
 __global__ void k_tables(Crystal c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
@@ -334,10 +340,36 @@ __device__ __forceinline__ unsigned row_bits_pre(const Crystal &c, const RateArg
   return bits;
 }
 
+// Window bits of one row of a queued block with the column records taken from LDS (cs: the
+// six (v, w) records of the column point as double2 pairs, shared by the lanes of the group).
+// b0 = orient 0 bits, b1 = orient 1 bits (mirror rows only); equal to those of row_bits_pre.
 template <int NB, int S2>
-__device__ __forceinline__ unsigned row_bits(const Crystal &c, const RateArgs &a, double aw,
-                                             int mur, int iqc, int orient) {
-  return row_bits_pre<NB, S2>(c, a, aw, c.mode4[mur], c.qbound[iqc], iqc, orient);
+__device__ __forceinline__ void row_bits_cols(const RateArgs &a, double aw, const double4 vr,
+                                              const double4 qb, const double2 *cs,
+                                              bool mirror_row, unsigned &b0, unsigned &b1) {
+  b0 = 0u;
+  b1 = 0u;
+  if (!(vr.w > 0.0)) return;
+  const double speed = sqrt(vr.x * vr.x + vr.y * vr.y + vr.z * vr.z);
+  const double lim = a.sqrt_c_win * (speed + qb.z) * (1.0 + 1e-6) + 1e-12;
+  auto dist = [&](double x) {
+    const double lo = x - qb.y, hi = x - qb.x;
+    return lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0);
+  };
+  const bool t0 = !(dist(add_signed(aw, vr.w, S2)) > lim);
+  const bool t1 = mirror_row && !(dist(aw - vr.w) > lim);
+  if (!t0 && !t1) return;
+  const double bw = add_signed(aw, vr.w, S2);
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    const double2 p0 = cs[2 * cc], p1 = cs[2 * cc + 1];
+    const double4 vc = make_double4(p0.x, p0.y, p1.x, p1.y);
+    double dw, s2;
+    if (vc.w > 0.0) {
+      if (t0 && window_keep(bw, vc.w, vr, vc, a.c_win, dw, s2)) b0 |= 1u << cc;
+      if (t1 && window_keep(add_signed(aw, vc.w, S2), vr.w, vc, vr, a.c_win, dw, s2)) b1 |= 1u << cc;
+    }
+  }
 }
 
 // What Gamma needs of a mode besides V: (v, w), 1/w and n0 at each temperature.
@@ -382,7 +414,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
     const int mr = q.x * NB + r, mc = q.y * NB + cc;
     mu2 = b >= NB ? mc : mr;
     mu3 = b >= NB ? mr : mc;
-    vi = g * NB * NB + r * NB + cc;
+    vi = g * xtile(NB, sizeof(CR)) + r * NB + cc;
   };
 #pragma unroll 1
   for (int i = lane; i < cnt; i += 64) {
@@ -454,9 +486,30 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   // weight of the channel (Eq. tao0), prefactor C4/N^2 and 1/(w w') of Eq. 4phgamma
   const double kw = WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
   const unsigned long long lt = (1ull << lane) - 1ull;
-  // q'' is dealt to the wavefronts in rounds of GPW consecutive points, so that every
+  const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
+  // ++ and --: q'' is scanned in ascending order of its lowest active frequency, and only as
+  // far as a row can pass the window.  A kept process has |dw| <= sqrt(c_win) |v'' - v'''|
+  // <= 2 sqrt(c_win) v_hi, with dw = aw + w'' - w''' (++) or aw - w'' - w''' (--), so its row
+  // frequency w'' is at most thr = w_hi - aw + win (++) or aw - w_lo + win (--).  The margins
+  // are far above the FP64 rounding of the exact test, so no kept process is skipped.
+  int nscan = c.N;
+  if (!MIRROR) {
+    const double win = 2.0 * a.sqrt_c_win * c.v_hi * (1.0 + 1e-6) + 1e-9 * (fabs(aw) + c.w_hi) + 1e-12;
+    const double thr = (S2 > 0 ? c.w_hi - aw : aw - c.w_lo) + win;
+    // count the sorted entries <= thr: whole 64ths of the list first, then the boundary one
+    const int seg = (c.N + 63) >> 6;
+    const bool le = lane * seg < c.N && c.qord_w[min(c.N, (lane + 1) * seg) - 1] <= thr;
+    const int full = __popcll(__ballot(le));
+    nscan = full * seg;
+    for (int i0 = 0; i0 < seg; i0 += 64) {
+      const int i = i0 + lane, p = full * seg + i;
+      const bool b = i < seg && p < c.N && c.qord_w[p] <= thr;
+      nscan += __popcll(__ballot(b));
+    }
+  }
+  // q'' (or the sorted list) is dealt to the wavefronts in rounds of GPW consecutive points, so that every
   // wavefront sees the whole range (the mirror-pair members are not spread evenly over it)
-  const int nk = (c.N + 4 * GPW - 1) / (4 * GPW);
+  const int nk = (nscan + 4 * GPW - 1) / (4 * GPW);
   constexpr int KSEG = QSEG / GPW;
   // the column point is fold(b3 + s'' q''), b3 = q + s' q'; DK = grid digits of the
   // per-round step 4 GPW of q''
@@ -468,50 +521,66 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
     const int z = wrap(b3.z + S2 * n2.z, c.g2);
     return x + c.g0 * (y + c.g1 * z);
   };
-  const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
   for (int k0 = 0; k0 < nk; k0 += KSEG) {
     const int k1 = min(nk, k0 + KSEG);
-    // phase 1: queue.  The grid digits of q'' advance arithmetically by DK per round (no
-    // index-table load), and the row and bound records of the next round are fetched
-    // while the current round is tested.
+    // phase 1: queue
     int cnt = 0;
-    int iq2 = (k0 * 4 + wave) * GPW + gw;
-    int4 d2 = c.qn[min(iq2, c.N - 1)];
-    int iq3 = fold_d(d2);
-    const bool live0 = !MIRROR && glane && iq2 < c.N;
-    double4 vr = live0 ? c.mode4[iq2 * NB + r] : make_double4(0.0, 0.0, 0.0, 0.0);
-    double4 qb = live0 ? c.qbound[iq3] : make_double4(0.0, 0.0, 0.0, 0.0);
-    for (int k = k0; k < k1; ++k) {
-      const int iq2c = iq2, iq3c = iq3;
-      const double4 vrc = vr, qbc = qb;
-      // next round
-      iq2 += 4 * GPW;
-      d2.x += DK.x;
-      const int cx = d2.x >= c.g0;
-      d2.x -= cx ? c.g0 : 0;
-      d2.y += DK.y + cx;
-      const int cy = d2.y >= c.g1;
-      d2.y -= cy ? c.g1 : 0;
-      d2.z += DK.z + cy;
-      iq3 = fold_d(d2);
-      if (!MIRROR && glane && k + 1 < k1 && iq2 < c.N) {
-        vr = c.mode4[iq2 * NB + r];
-        qb = c.qbound[iq3];
+    if constexpr (MIRROR) {
+      // every q'' in grid order, one block of each mirror pair; the grid digits of q''
+      // advance arithmetically by DK per round (no index-table load)
+      int iq2 = (k0 * 4 + wave) * GPW + gw;
+      int4 d2 = c.qn[min(iq2, c.N - 1)];
+      for (int k = k0; k < k1; ++k) {
+        const int iq2c = iq2, iq3c = fold_d(d2);
+        iq2 += 4 * GPW;
+        d2.x += DK.x;
+        const int cx = d2.x >= c.g0;
+        d2.x -= cx ? c.g0 : 0;
+        d2.y += DK.y + cx;
+        const int cy = d2.y >= c.g1;
+        d2.y -= cy ? c.g1 : 0;
+        d2.z += DK.z + cy;
+        const bool lead = glane && iq2c < c.N && iq2c <= iq3c && r == 0;
+        const unsigned long long lb = __ballot(lead);
+        if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
+        cnt += __popcll(lb);
       }
-      bool keep = false;
-      if (glane && iq2c < c.N) {
-        if (MIRROR) {
-          keep = iq2c <= iq3c;
-        } else {
+    } else {
+      // the first nscan points of the sorted list, the blocks with a surviving process; the
+      // list entry two rounds ahead and the row and bound records of the next round are
+      // fetched while the current round is tested
+      constexpr int STEP = 4 * GPW;
+      int p = (k0 * 4 + wave) * GPW + gw;
+      const int4 s0 = c.qord[min(p, c.N - 1)];
+      int4 sn = c.qord[min(p + STEP, c.N - 1)];
+      int iq2 = s0.x, iq3 = fold_d(make_int4(s0.y, s0.z, s0.w, 0));
+      bool live = glane && p < nscan;
+      double4 vr = live ? c.mode4[iq2 * NB + r] : make_double4(0.0, 0.0, 0.0, 0.0);
+      double4 qb = live ? c.qbound[iq3] : make_double4(0.0, 0.0, 0.0, 0.0);
+      for (int k = k0; k < k1; ++k) {
+        const int iq2c = iq2, iq3c = iq3;
+        const bool livec = live;
+        const double4 vrc = vr, qbc = qb;
+        p += STEP;
+        iq2 = sn.x;
+        iq3 = fold_d(make_int4(sn.y, sn.z, sn.w, 0));
+        sn = c.qord[min(p + STEP, c.N - 1)];
+        live = glane && k + 1 < k1 && p < nscan;
+        if (live) {
+          vr = c.mode4[iq2 * NB + r];
+          qb = c.qbound[iq3];
+        }
+        bool keep = false;
+        if (livec) {
           const unsigned bits = row_bits_pre<NB, S2>(c, a, aw, vrc, qbc, iq3c, 0);
           const unsigned long long bal = __ballot(bits != 0u);
           keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
         }
+        const bool lead = keep && r == 0;
+        const unsigned long long lb = __ballot(lead);
+        if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
+        cnt += __popcll(lb);
       }
-      const bool lead = keep && r == 0;
-      const unsigned long long lb = __ballot(lead);
-      if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
-      cnt += __popcll(lb);
     }
     wave_sync();
     // phase 2: contract the queued blocks, GPW at a time (one per lane group), then
@@ -531,10 +600,16 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
           divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
         }
         iq3 = fold_d(n2);
-        const int mur = iq2 * NB + r;
-        bA = row_bits<NB, S2>(c, a, aw, mur, iq3, 0);
-        bB = (MIRROR && iq2 != iq3) ? row_bits<NB, S2>(c, a, aw, mur, iq3, 1) : 0u;
+        // lane r reads column record r; the group shares the six through its tile
+        const double4 vc = c.mode4[iq3 * NB + r];
+        double2 *cs = reinterpret_cast<double2 *>(Xg);
+        cs[2 * r] = make_double2(vc.x, vc.y);
+        cs[2 * r + 1] = make_double2(vc.z, vc.w);
       }
+      wave_sync();
+      if (act)
+        row_bits_cols<NB, S2>(a, aw, c.mode4[iq2 * NB + r], c.qbound[iq3],
+                              reinterpret_cast<const double2 *>(Xg), MIRROR && iq2 != iq3, bA, bB);
       const unsigned long long bal = __ballot((bA | bB) != 0u);
       const bool blk = act && ((bal >> (gw * NB)) & GMASK) != 0ull;
       if (blk && r == 0) acc.blocks += 1;
@@ -584,8 +659,9 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
   constexpr int GPW = 64 / NB;
   constexpr int NGRP = 4 * GPW;
   CR *W = reinterpret_cast<CR *>(smem);                 // [2][ng][9]
-  CR *X = W + 2 * c.ng * 9;                             // [NGRP][NB][NB]
-  CR *P = X + NGRP * NB * NB;                           // [NGRP][nd]
+  constexpr int XT = xtile(NB, sizeof(CR));
+  CR *X = W + 2 * c.ng * 9;                             // [NGRP][XT]
+  CR *P = X + NGRP * XT;                                // [NGRP][nd]
   int2 *Gq = reinterpret_cast<int2 *>(P + NGRP * c.nd); // [NGRP] current block of each group
   int *sg_d = reinterpret_cast<int *>(Gq + NGRP);       // [ng]
   int *skl = sg_d + c.ng;                               // [nat*nat + 1]
@@ -596,10 +672,10 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
   const int gw = lane / NB, r = lane - gw * NB;
   const bool glane = gw < GPW;
   const int G = wave * GPW + gw;
-  CR *Xg = X + (size_t)(glane ? G : 0) * NB * NB;
+  CR *Xg = X + (size_t)(glane ? G : 0) * XT;
   CR *Pg = P + (size_t)(glane ? G : 0) * c.nd;
   int *Qw = Q + wave * QSEG;
-  const CR *Xw = X + (size_t)wave * GPW * NB * NB;
+  const CR *Xw = X + (size_t)wave * GPW * XT;
   int2 *Gqw = Gq + wave * GPW;
   unsigned short *Lw = L + wave * LSEG;
   for (int i = tid; i < c.ng; i += 256) sg_d[i] = c.g_d[i];
@@ -805,7 +881,7 @@ __global__ void k_zero(unsigned long long *p, size_t n) {
 size_t rate_lds_bytes(const Crystal &c, int fp32, int NT) {
   const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
   const int NB = c.nb, GPW = 64 / NB;
-  const size_t lds = cb * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * NB * NB + (size_t)4 * GPW * c.nd) +
+  const size_t lds = cb * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * xtile(NB, (int)cb) + (size_t)4 * GPW * c.nd) +
                      sizeof(int2) * (size_t)4 * GPW +
                      sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1 + 4 * QSEG) +
                      sizeof(unsigned short) * (size_t)4 * LSEG;

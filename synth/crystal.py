@@ -132,6 +132,14 @@ def layered_three_atom(a_h: float = 2.82, c_h: float = 14.05,
                    np.array(masses, dtype=float), [(np.eye(3), np.zeros(3))])
 
 
+def fcc_one_atom(a: float = 3.6, mass: float = 63.5) -> Crystal:
+    """One-atom FCC cell (3 branches), primitive vectors a/2 (0,1,1), (1,0,1), (1,1,0).
+    Only the identity is used as a symmetry operation."""
+    A = 0.5 * a * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+    return Crystal("fcc_one_atom", A, np.zeros((1, 3)), np.array([mass]),
+                   [(np.eye(3), np.zeros(3))])
+
+
 def check_ops(cr: Crystal, tol: float = 1e-8) -> None:
     """Assert every stored operation maps every site onto a site."""
     for T, t in cr.ops:

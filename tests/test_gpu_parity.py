@@ -261,6 +261,23 @@ def test_three_atom_cell(fp4):
     assert _rel(r32, r_o) <= RTOL32
 
 
+def test_one_atom_cell(fp4):
+    """Three branches (the 1-atom instantiation of the kernels, whose group tiles are sized by
+    the shared column records rather than by the 3x3 block): an FCC one-atom cell on a 3x3x4
+    grid, every mode, two temperatures: counts exact, rates within 1e-10, FP32 within 1e-4."""
+    _say("case: one-atom FCC cell 3x3x4")
+    from synth import configs
+    inst = configs.one_atom(grid=(3, 3, 4))
+    r_o, _, c_o = _oracle(inst, inst.T, 1.0, 7)
+    with _ctx(fp4, inst) as c:
+        r, _, cnt = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+        r32, _, cnt32 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP32)
+    assert c_o.sum() > 0
+    assert np.array_equal(cnt, c_o) and np.array_equal(cnt32, c_o)
+    assert _rel(r, r_o) <= RTOL64
+    assert _rel(r32, r_o) <= RTOL32
+
+
 def test_large_grid_properties(fp4):
     """The 16x16x16 workload (24 576 modes, the largest benchmarked grid), where the oracle
     is out of reach per mode: properties that hold at any size on 32 sampled q points and
