@@ -163,12 +163,41 @@ __global__ void k_precontract(Crystal c, const int *targets, int nt, CR *U) {
 
 // W[s][g][gamma*3 + theta], s = 0 for s' = + and 1 for s' = -:
 //   sum over combos c of g, beta: U_c[beta][gt] (E[q'][j'][3 j_c + beta] exp(i q'.a_c))^(s')
+// The slot-2 factors p[c][beta] = E[q'][j'][3 j_c + beta] exp(i q'.a_c), shared by the nine
+// entries of a group, are formed once into `stage` (LDS, free while W is built) when it holds
+// them, so the entry loop reads only U from memory.
 template <typename R>
 __device__ void build_W(const Crystal &c, const typename CT<R>::T *Ut, int iq1, int j1,
-                        typename CT<R>::T *W, int tid, int nthr) {
+                        typename CT<R>::T *W, typename CT<R>::T *stage, int stage_cap, int tid,
+                        int nthr) {
   using CR = typename CT<R>::T;
   const CR *e2 = Etab<R>(c) + ((size_t)iq1 * c.nb + j1) * c.nb;
   const int tot = c.ng * 9;
+  if (3 * c.nc <= stage_cap) {
+    for (int i = tid; i < 3 * c.nc; i += nthr) {
+      const int ci = i / 3, be = i - 3 * ci;
+      const CR ph = fromd<CR>(c.PHA64[(size_t)iq1 * c.na + c.c_a[ci]]);
+      stage[i] = cmul(e2[3 * c.c_jat[ci] + be], ph);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < tot; idx += nthr) {
+      const int g = idx / 9, gt = idx - 9 * g;
+      CR ap = czero<CR>(), am = czero<CR>();
+      for (int ci = c.c_start[g]; ci < c.c_start[g + 1]; ++ci) {
+        const CR *u = Ut + (size_t)ci * 27 + gt;
+#pragma unroll
+        for (int be = 0; be < 3; ++be) {
+          const CR p = stage[3 * ci + be];
+          const CR uu = u[9 * be];
+          cmac(ap, uu, p);
+          cmac_cb(am, uu, p);
+        }
+      }
+      W[idx] = ap;
+      W[tot + idx] = am;
+    }
+    return;
+  }
   for (int idx = tid; idx < tot; idx += nthr) {
     const int g = idx / 9, gt = idx - 9 * g;
     CR ap = czero<CR>(), am = czero<CR>();
@@ -296,53 +325,18 @@ struct Acc {
   unsigned blocks;
 };
 
-// Window-prefilter bits of one row of a branch block.  Lane r owns row mode mu_r = (q'', r);
-// column cc is (q''', cc).  orient 0 tests the processes (lambda'' = row, lambda''' = column),
-// orient 1 the mirrored ones (lambda'' = column, lambda''' = row) of the redistribution
-// channel.  Each candidate is evaluated in the same FP64 order as a stand-alone process.
+// Window-prefilter bits of one row of a branch block.  Lane r owns row mode mu_r = (q'', r)
+// with record vr; column cc is (q''', cc), whose (v, w) records the lanes of the group share
+// through LDS (cs: record cc as the double2 pair cs[2cc], cs[2cc+1]).  b0 tests the processes
+// (lambda'' = row, lambda''' = column), b1 (mirror rows of the redistribution channel only)
+// the mirrored ones (lambda'' = column, lambda''' = row).  Each candidate is evaluated in the
+// same FP64 order as a stand-alone process.
 //
 // A row is skipped without testing its candidates when no candidate can pass: dw of the row
-// lies in x - [w_min, w_max] of q''' (active branches) and a kept process needs
-// |dw| <= sqrt(c_win) |v'' - v'''| <= sqrt(c_win) (|v_row| + v_max(q''')); the bound is
-// applied with a relative margin of 1e-6, far above FP64 rounding, so it never drops a
-// process the exact test would keep.
-template <int NB, int S2>
-__device__ __forceinline__ unsigned row_bits_pre(const Crystal &c, const RateArgs &a, double aw,
-                                                 const double4 vr, const double4 qb, int iqc,
-                                                 int orient) {
-  if (!(vr.w > 0.0)) return 0u;
-  {
-    // qb = (w_min, w_max, v_max, 0) over the active branches of the column point
-    const double x = orient == 0 ? add_signed(aw, vr.w, S2) : aw - vr.w;
-    const double lo = x - qb.y, hi = x - qb.x;
-    const double dist = lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0);
-    const double speed = sqrt(vr.x * vr.x + vr.y * vr.y + vr.z * vr.z);
-    if (dist > a.sqrt_c_win * (speed + qb.z) * (1.0 + 1e-6) + 1e-12) return 0u;
-  }
-  unsigned bits = 0u;
-  if (orient == 0) {
-    const double bw = add_signed(aw, vr.w, S2);
-#pragma unroll
-    for (int cc = 0; cc < NB; ++cc) {
-      const double4 vc = c.mode4[iqc * NB + cc];
-      double dw, s2;
-      if (vc.w > 0.0 && window_keep(bw, vc.w, vr, vc, a.c_win, dw, s2)) bits |= 1u << cc;
-    }
-  } else {
-#pragma unroll
-    for (int cc = 0; cc < NB; ++cc) {
-      const double4 vc = c.mode4[iqc * NB + cc];
-      double dw, s2;
-      if (vc.w > 0.0 && window_keep(add_signed(aw, vc.w, S2), vr.w, vc, vr, a.c_win, dw, s2))
-        bits |= 1u << cc;
-    }
-  }
-  return bits;
-}
-
-// Window bits of one row of a queued block with the column records taken from LDS (cs: the
-// six (v, w) records of the column point as double2 pairs, shared by the lanes of the group).
-// b0 = orient 0 bits, b1 = orient 1 bits (mirror rows only); equal to those of row_bits_pre.
+// lies in x - [w_min, w_max] of q''' (qb = (w_min, w_max, v_max, 0) over its active
+// branches) and a kept process needs |dw| <= sqrt(c_win) |v'' - v'''| <= sqrt(c_win)
+// (|v_row| + v_max(q''')); the bound is applied with a relative margin of 1e-6, far above
+// FP64 rounding, so it never drops a process the exact test would keep.
 template <int NB, int S2>
 __device__ __forceinline__ void row_bits_cols(const RateArgs &a, double aw, const double4 vr,
                                               const double4 qb, const double2 *cs,
@@ -555,12 +549,20 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       int4 sn = c.qord[min(p + STEP, c.N - 1)];
       int iq2 = s0.x, iq3 = fold_d(make_int4(s0.y, s0.z, s0.w, 0));
       bool live = glane && p < nscan;
-      double4 vr = live ? c.mode4[iq2 * NB + r] : make_double4(0.0, 0.0, 0.0, 0.0);
-      double4 qb = live ? c.qbound[iq3] : make_double4(0.0, 0.0, 0.0, 0.0);
+      const double4 z4 = make_double4(0.0, 0.0, 0.0, 0.0);
+      double4 vr = live ? c.mode4[iq2 * NB + r] : z4;
+      double4 qb = live ? c.qbound[iq3] : z4;
+      double4 vc = live ? c.mode4[iq3 * NB + r] : z4;
+      double2 *cs = reinterpret_cast<double2 *>(Xg);
       for (int k = k0; k < k1; ++k) {
-        const int iq2c = iq2, iq3c = iq3;
         const bool livec = live;
+        const int iq2c = iq2;
         const double4 vrc = vr, qbc = qb;
+        // lane r holds column record r of the round; the group shares the six through its tile
+        if (livec) {
+          cs[2 * r] = make_double2(vc.x, vc.y);
+          cs[2 * r + 1] = make_double2(vc.z, vc.w);
+        }
         p += STEP;
         iq2 = sn.x;
         iq3 = fold_d(make_int4(sn.y, sn.z, sn.w, 0));
@@ -569,13 +571,17 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         if (live) {
           vr = c.mode4[iq2 * NB + r];
           qb = c.qbound[iq3];
+          vc = c.mode4[iq3 * NB + r];
         }
+        wave_sync();
         bool keep = false;
         if (livec) {
-          const unsigned bits = row_bits_pre<NB, S2>(c, a, aw, vrc, qbc, iq3c, 0);
-          const unsigned long long bal = __ballot(bits != 0u);
+          unsigned b0, b1;
+          row_bits_cols<NB, S2>(a, aw, vrc, qbc, cs, false, b0, b1);
+          const unsigned long long bal = __ballot(b0 != 0u);
           keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
         }
+        wave_sync();
         const bool lead = keep && r == 0;
         const unsigned long long lb = __ballot(lead);
         if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
@@ -708,7 +714,7 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
         const double w1 = c.omega[mu1];
         if (!(w1 > 0.0)) continue;
         __syncthreads();
-        build_W<R>(c, Ut, iq1, j1, W, tid, 256);
+        build_W<R>(c, Ut, iq1, j1, W, X, NGRP * (XT + c.nd), tid, 256);
         __syncthreads();
         double n1[NT];
 #pragma unroll
@@ -853,7 +859,7 @@ __global__ __launch_bounds__(64) void k_debug_v(Crystal c, const int *quads, con
   const int *qd = quads + 8 * p;
   const int iq = qd[0], iq1 = qd[2], j1 = qd[3], iq2 = qd[4], j2 = qd[5], j3 = qd[6], ch = qd[7];
   const CR *Ut = U + (size_t)tslot[p] * c.nc * 27;
-  build_W<R>(c, Ut, iq1, j1, W, tid, 64);
+  build_W<R>(c, Ut, iq1, j1, W, nullptr, 0, tid, 64);
   __syncthreads();
   if (tid >= NB) return;
   const int s1 = ch == 2 ? -1 : 1, s2 = ch == 0 ? 1 : -1;
