@@ -47,6 +47,15 @@ __device__ __forceinline__ void divmod_small(int x, int g, float inv_g, int &q, 
   }
 }
 
+// A value that is the same in every lane (work-group constants such as the frequencies of
+// lambda and lambda'), moved to scalar registers so it takes no vector register
+__device__ __forceinline__ double uniform_d(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -697,28 +706,28 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
     acc.cnt[ch] = 0;
   }
   acc.blocks = 0;
-  const double w = c.omega[mu];
+  const double w = uniform_d(c.omega[mu]);
   __syncthreads();
   if (w > 0.0) {
     const int4 nq = c.qn[iq];
     const CR *Ut = reinterpret_cast<const CR *>(a.U) + (size_t)t * c.nc * 27;
     double invn[NT];
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) invn[tt] = (tt < a.nT) ? a.inv_occ[(size_t)tt * c.N * NB + mu] : 0.0;
+    for (int tt = 0; tt < NT; ++tt) invn[tt] = (tt < a.nT) ? uniform_d(a.inv_occ[(size_t)tt * c.N * NB + mu]) : 0.0;
     const int q1b = chunk * a.qchunk;
     const int q1e = min(c.N, q1b + a.qchunk);
     for (int iq1 = q1b; iq1 < q1e; ++iq1) {
       const int4 nq1 = c.qn[iq1];
       for (int j1 = 0; j1 < NB; ++j1) {
         const int mu1 = iq1 * NB + j1;
-        const double w1 = c.omega[mu1];
+        const double w1 = uniform_d(c.omega[mu1]);
         if (!(w1 > 0.0)) continue;
         __syncthreads();
         build_W<R>(c, Ut, iq1, j1, W, X, NGRP * (XT + c.nd), tid, 256);
         __syncthreads();
         double n1[NT];
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt) n1[tt] = (tt < a.nT) ? a.occ[(size_t)tt * c.N * NB + mu1] : 0.0;
+        for (int tt = 0; tt < NT; ++tt) n1[tt] = (tt < a.nT) ? uniform_d(a.occ[(size_t)tt * c.N * NB + mu1]) : 0.0;
         if (a.mask & 1u)
           channel_blocks<R, NB, NT, 0>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
         if (a.mask & 2u)
