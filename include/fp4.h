@@ -135,9 +135,10 @@ int fp4_compute_rates4_subset(fp4_ctx *ctx, const double *T, int32_t nT, double 
  *   hip_stream   a hipStream_t of the context's device (NULL = the null stream)
  *   d_rates      DEVICE [nT][nq*nb] doubles (required)
  *   d_rates_by_channel DEVICE [nT][3][nq*nb] or NULL;  d_counts DEVICE [nq*nb][3] or NULL
- * All work is enqueued on hip_stream; the call returns without waiting.  The context's
- * internal buffers are reused by the next call, so calls on one context must not overlap
- * on different streams. */
+ * The rate work is enqueued on hip_stream and the call returns without waiting for it; the
+ * staging of the target list, and on the first call after a load the per-q tables, run on
+ * the context's own stream and are waited for.  The context's internal buffers are reused
+ * by the next call, so calls on one context must not overlap on different streams. */
 int fp4_compute_rates4_async(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
                              uint32_t mask, int32_t precision, void *hip_stream,
                              double *d_rates, double *d_rates_by_channel, int64_t *d_counts);

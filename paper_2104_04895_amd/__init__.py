@@ -61,6 +61,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2104_04895_amd.build` (no CPU fallback exists)")
+        # PyTorch ships its own HIP runtime.  Loading it first makes the library bind to that
+        # same runtime; a second runtime loaded before torch initialises leaves torch without
+        # devices, which breaks torch streams and tensors passed to the async entry point.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, i32, u32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
         L.fp4_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]

@@ -773,6 +773,8 @@ int fp4_compute_rates4_async(fp4_ctx *ctx, const double *T, int32_t nT, double s
     // the target list and temperatures are staged through the context's stream first
     if ((rc = upload(ctx, ctx->d_targets, tl.data(), tl.size()))) return rc;
     FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // per-q tables (after a load) are built on the context's own stream, never the caller's
+    if ((rc = ensure_tables(ctx))) return rc;
     const hipStream_t keep = ctx->stream;
     ctx->stream = s;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;

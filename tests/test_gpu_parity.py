@@ -160,6 +160,66 @@ def test_closed_form_gamma_only(fp4):
     assert _rel(r, r_o) <= RTOL64
 
 
+def test_flat_bands_zero_velocity(fp4):
+    """Dispersionless branches (10, 20, 30 rad/ps at every q) with zero group velocity on a
+    2x2x2 grid: the window keeps exactly the processes with dw = 0 (e.g. 10 + 10 + 10 - 30),
+    which sit on the edge of every frequency bound the kernel applies (row cull, sorted
+    q'' scan).  Counts must equal the oracle's and rates agree to 1e-10."""
+    _say("case: flat bands, zero velocity, 2x2x2")
+    import itertools
+    rng = np.random.default_rng(11)
+    C = rng.standard_normal((3, 3, 3, 3))
+    C = sum(np.transpose(C, p) for p in itertools.permutations(range(4))) / 24.0
+    nq = 8
+    w = np.tile(np.array([10.0, 20.0, 30.0]), (nq, 1))
+    evec = np.zeros((nq, 3, 1, 3), dtype=complex)
+    for j in range(3):
+        evec[:, j, 0, j] = 1.0
+    vel = np.zeros((nq, 3, 3))
+    atoms = np.zeros((1, 4), dtype=np.int32)
+    cells = np.zeros((1, 3, 3), dtype=np.int32)
+    A = np.eye(3) * 3.0
+    mo = oracle.Model((2, 2, 2), [12.0], w, evec, vel, atoms, cells, C.reshape(1, 81))
+    r_o, _, c_o = oracle.rates4(mo, [300.0, 900.0], 1.0, 7, 0.3)
+    with fp4.Context(0) as c:
+        c.load_lattice(A, (2, 2, 2), [12.0], 0.3)
+        c.load_modes(w, evec, vel)
+        c.load_fc4(atoms, cells, C.reshape(1, 81))
+        r, _, cnt = c.compute_rates4([300.0, 900.0], 1.0, 7, fp4.FP4_FP64)
+        r32, _, cnt32 = c.compute_rates4([300.0, 900.0], 1.0, 7, fp4.FP4_FP32)
+    assert c_o.sum() > 0 and c_o[:, 0].sum() > 0 and c_o[:, 2].sum() > 0
+    assert np.array_equal(cnt, c_o) and np.array_equal(cnt32, c_o)
+    assert _rel(r, r_o) <= RTOL64
+    assert _rel(r32, r_o) <= RTOL32
+
+
+def test_async_on_caller_stream(fp4, small):
+    """fp4_compute_rates4_async on a torch stream into torch device tensors, as the first call
+    after the loads (the per-q tables are built inside it) and again at other temperatures:
+    identical to the synchronous call, channel rates summing to the total."""
+    import torch
+    _say("case: async entry point on a caller stream")
+    nm = small.nmodes
+    dev = torch.device("cuda:0")
+    st = torch.cuda.Stream(device=dev)
+    out = []
+    with _ctx(fp4, small) as c:
+        for T in ([300.0], [150.0, 600.0, 1200.0]):
+            d_r = torch.empty((len(T), nm), dtype=torch.float64, device=dev)
+            d_ch = torch.empty((len(T), 3, nm), dtype=torch.float64, device=dev)
+            d_n = torch.empty((nm, 3), dtype=torch.int64, device=dev)
+            c.compute_rates4_async(T, 1.0, 7, fp4.FP4_FP64, st.cuda_stream, d_r.data_ptr(),
+                                   d_ch.data_ptr(), d_n.data_ptr())
+            st.synchronize()
+            out.append((T, d_r.cpu().numpy(), d_ch.cpu().numpy(), d_n.cpu().numpy()))
+    with _ctx(fp4, small) as c:
+        for T, r, rch, n in out:
+            r_s, rch_s, n_s = c.compute_rates4(T, 1.0, 7, fp4.FP4_FP64, by_channel=True)
+            assert np.array_equal(n, n_s)
+            assert np.array_equal(r, r_s) and np.array_equal(rch, rch_s)
+            assert _rel(rch.sum(axis=1), r) <= 1e-12
+
+
 def test_properties_on_gpu(fp4, small):
     """Invariants that hold at any size, checked on the HIP path itself: time reversal
     (counts equal, rates equal to rounding), mask additivity, exact x4 under Phi -> 2 Phi."""
