@@ -268,6 +268,21 @@ hipEvent_t pool_event(fp4_ctx *ctx, size_t i) {
   return ctx->ev_pool[i];
 }
 
+// Default q' points per work item for `nt` targets: enough items to fill the GPU (~8192),
+// at most 16 q' per item, so that the ~96 work-groups resident on an XCD span few targets
+// (items are mapped to XCDs in contiguous ranges), within a 1 GiB partial buffer.
+int auto_qchunk(const fp4_ctx *ctx, int nt, int nT) {
+  long long nchunk = (8192 + nt - 1) / nt;
+  if (nchunk < 1) nchunk = 1;
+  if (nchunk > ctx->N) nchunk = ctx->N;
+  int qchunk = (int)((ctx->N + nchunk - 1) / nchunk);
+  qchunk = std::min(qchunk, 16);
+  while (qchunk < ctx->N &&
+         (size_t)nt * (size_t)((ctx->N + qchunk - 1) / qchunk) * 3 * nT * sizeof(double) > ((size_t)1 << 30))
+    qchunk *= 2;
+  return qchunk;
+}
+
 // Enqueue the whole rate computation for `nt` targets (device list d_targets) on `s`.
 // Device outputs: rates [nT][nt], rates_ch [nT][3][nt] (nullable), counts [nt][3] (nullable).
 int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int precision,
@@ -285,20 +300,7 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
                                        (double *)ctx->d_occ.p, (double *)ctx->d_iocc.p, s));
 
   // work decomposition: q'-chunks per target so that a launch has enough work-groups
-  int qchunk = ctx->qchunk;
-  if (qchunk <= 0) {
-    long long want = 8192;
-    long long nchunk = (want + nt - 1) / nt;
-    if (nchunk < 1) nchunk = 1;
-    if (nchunk > ctx->N) nchunk = ctx->N;
-    qchunk = (int)((ctx->N + nchunk - 1) / nchunk);
-    // at most 16 q' per work-group, so that the ~96 work-groups resident on an XCD span
-    // few targets (k_rates maps consecutive items to one XCD), within a 1 GiB partial buffer
-    qchunk = std::min(qchunk, 16);
-    while (qchunk < ctx->N &&
-           (size_t)nt * (size_t)((ctx->N + qchunk - 1) / qchunk) * 3 * nT * sizeof(double) > ((size_t)1 << 30))
-      qchunk *= 2;
-  }
+  int qchunk = ctx->qchunk > 0 ? ctx->qchunk : auto_qchunk(ctx, nt, nT);
   if (qchunk > ctx->N) qchunk = ctx->N;
   const int nchunk = (ctx->N + qchunk - 1) / qchunk;
   const size_t cbytes = fp32 ? sizeof(float2) : sizeof(double2);
@@ -1125,7 +1127,7 @@ struct fp4_batch {
   hipGraphExec_t exec = nullptr;
   std::string key;
   DevBuf d_inst[4];       // instance tables of the branch-count classes nb = 3, 6, 9, 12
-  DevBuf d_counter;       // one work counter per class
+  DevBuf d_counter;       // work queue counters, kClassCounters per class
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double ms_last = 0.0;
   long long graph_builds = 0, graph_launches = 0;
@@ -1211,7 +1213,7 @@ int enqueue_batch(fp4_batch *b, std::vector<fp4::BatchInst> (&cls)[4], int fp32,
     FP4_HIP(b, fp4::launch_precontract(bi.c, bi.a.targets, bi.a.nt, fp32, ctx->d_U.p, s));
     FP4_HIP(b, fp4::launch_zero(ctx->d_blocks.p, sizeof(unsigned long long), s));
   }
-  FP4_HIP(b, fp4::launch_zero(b->d_counter.p, 4 * sizeof(unsigned long long), s));
+  FP4_HIP(b, fp4::launch_zero(b->d_counter.p, 4 * fp4::kClassCounters * sizeof(unsigned long long), s));
   for (int k = 0; k < 4; ++k) {
     if (cls[k].empty()) continue;
     long long total = 0;
@@ -1221,7 +1223,7 @@ int enqueue_batch(fp4_batch *b, std::vector<fp4::BatchInst> (&cls)[4], int fp32,
       lds = std::max(lds, fp4::batch_lds_bytes(bi.c, fp32, nT));
     }
     hipError_t e = fp4::launch_batch((const fp4::BatchInst *)b->d_inst[k].p, (int)cls[k].size(), total,
-                                     (unsigned long long *)b->d_counter.p + k, lds, fp32,
+                                     (unsigned long long *)b->d_counter.p + (size_t)k * fp4::kClassCounters, lds, fp32,
                                      3 * (k + 1), nT, nullptr, s);
     if (e == hipErrorInvalidValue)
       return b->fail(FP4_E_UNSUPPORTED, "an instance needs more LDS than a work-group has");
@@ -1260,7 +1262,7 @@ int build_classes(fp4_batch *b, const std::vector<fp4_ctx *> &ctxs,
     cls[k].push_back(insts[o]);
   }
   int rc;
-  if ((rc = ensure(ctxs[0], b->d_counter, 4 * sizeof(unsigned long long)))) return b->fail(rc, ctxs[0]->err);
+  if ((rc = ensure(ctxs[0], b->d_counter, 4 * fp4::kClassCounters * sizeof(unsigned long long)))) return b->fail(rc, ctxs[0]->err);
   for (int k = 0; k < 4; ++k) {
     if (cls[k].empty()) continue;
     if ((rc = ensure(ctxs[0], b->d_inst[k], cls[k].size() * sizeof(fp4::BatchInst)))) return b->fail(rc, ctxs[0]->err);
@@ -1341,7 +1343,7 @@ int fp4_batch_compute(fp4_batch *b, const double *T, int32_t nT, double scalebro
       const int nm = b->ctxs[i]->N * b->ctxs[i]->nb;
       targets[i].resize(nm);
       for (int m = 0; m < nm; ++m) targets[i][m] = m;
-      qchunks[i] = b->ctxs[i]->qchunk > 0 ? b->ctxs[i]->qchunk : 16;
+      qchunks[i] = b->ctxs[i]->qchunk > 0 ? b->ctxs[i]->qchunk : auto_qchunk(b->ctxs[i], nm, nT);
     }
     std::vector<fp4::BatchInst> insts;
     std::vector<fp4::BatchInst> cls[4];

@@ -69,6 +69,12 @@ struct RateArgs {
   unsigned long long *blocks; // [1] contracted branch blocks (atomic)
 };
 
+// Work queues of a persistent batched launch: one counter per XCD range of the item list,
+// 128 bytes apart, per branch-count class.
+constexpr int kBatchQueues = 8;
+constexpr int kQueueStride = 16;   // unsigned long long
+constexpr int kClassCounters = kBatchQueues * kQueueStride;
+
 // One crystal of a persistent batched launch; items item0 .. item0 + nt*nchunk - 1.
 struct BatchInst {
   Crystal c;

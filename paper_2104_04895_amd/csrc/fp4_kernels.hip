@@ -795,8 +795,8 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 && NB <= 6) ? 4 : 3) void k_ra
 }
 
 // Persistent form over several crystals with the same branch count (uneven grids, quartet
-// lists and mode counts): every work-group takes (instance, target, q'-chunk) items from one
-// global atomic counter until the counter passes the total; items are numbered instance by
+// lists and mode counts): every work-group takes (instance, target, q'-chunk) items from
+// atomic work queues (below) until all are exhausted; items are numbered instance by
 // instance (the host orders the instances by cost per item, most expensive first).  Crystals
 // of different branch counts run as separate persistent kernels of the same graph.
 template <typename R, int NB, int NT>
@@ -805,9 +805,31 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 && NB <= 6) ? 4 : 3) void k_ra
                                                         unsigned long long *counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long item_s;
+  // Work-groups reach the XCDs round-robin by blockIdx, and the item list is target-major.
+  // The list is cut into one contiguous range per XCD with its own counter: a work-group
+  // takes items of its XCD's range first (the work-groups resident on an XCD then share
+  // targets, whose precontraction U stays in that XCD's L2), then those of the following
+  // ranges in turn.  Every item is handed out once; a work-group stops after finding all
+  // ranges exhausted.
+  const int home = (int)(blockIdx.x % kBatchQueues);
+  const long long q = total / kBatchQueues, rem = total % kBatchQueues;
+  int visited = 0;   // ranges found exhausted (thread 0)
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) {
+      long long it = total;
+      while (visited < kBatchQueues) {
+        const int x = (home + visited) % kBatchQueues;
+        const long long lo = x * q + (x < rem ? x : rem), n = q + (x < rem ? 1 : 0);
+        const long long k = (long long)atomicAdd(counter + (size_t)x * kQueueStride, 1ull);
+        if (k < n) {
+          it = lo + k;
+          break;
+        }
+        ++visited;
+      }
+      item_s = it;
+    }
     __syncthreads();
     // the item and the instance index are wave-uniform: keep them (and so the instance
     // descriptor loads) in scalar registers
