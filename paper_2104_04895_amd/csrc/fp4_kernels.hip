@@ -394,12 +394,15 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
 }
 
 // Gamma (Eq. 4phgamma) of a compacted list of kept processes of the wavefront's blocks,
-// accumulated into the lane's FP64 partial rates.  Entry i of L is (s << 5) | b for the
-// process of source lane s = (group g, row r) and kept bit b: b < NB is the process
-// (lambda'' = (q''_g, r), lambda''' = (q'''_g, b)), b >= NB the mirrored one
-// (lambda'' = (q'''_g, b - NB), lambda''' = (q''_g, r)).  V is read from the group's tile,
-// (q''_g, q'''_g) from Gq.  Consecutive lanes take consecutive entries, so every lane has
-// work while the list lasts.
+// accumulated into the lane's FP64 partial rates.  Entry i of L is (s << 6) | b for source
+// lane s = (group g, row r) and code b: b < NB is the process (lambda'' = (q''_g, r),
+// lambda''' = (q'''_g, b)), NB <= b < 2 NB the mirrored one (lambda'' = (q'''_g, b - NB),
+// lambda''' = (q''_g, r)), b >= 2 NB both of column b - 2 NB (redistribution channel, both
+// kept).  The two members of a mirror pair share |V| (V transposed), |v'' - v'''| and so
+// sigma, 1/(w'' w''') and the occupation factor; one evaluation serves both, each with its
+// own dw formed in its stand-alone order and its own Gaussian.  V is read from the group's
+// tile, (q''_g, q'''_g) from Gq.  Consecutive lanes take consecutive entries, so every lane
+// has work while the list lasts.
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const unsigned short *L, int cnt, int lane,
@@ -408,28 +411,36 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
   constexpr int S2 = (CH == 0) ? 1 : -1;
-  auto decode = [&](int i, int &mu2, int &mu3, int &vi) {
+  auto decode = [&](int i, int &mu2, int &mu3, int &vi, bool &pair) {
     const unsigned d = L[i];
-    const int s = (int)(d >> 5), b = (int)(d & 31u);
+    const int s = (int)(d >> 6), b = (int)(d & 63u);
     const int g = s / NB, r = s - g * NB;
     const int2 q = Gq[g];
-    const int cc = b >= NB ? b - NB : b;
+    const bool mir = b >= NB && b < 2 * NB;
+    pair = b >= 2 * NB;
+    const int cc = pair ? b - 2 * NB : (mir ? b - NB : b);
     const int mr = q.x * NB + r, mc = q.y * NB + cc;
-    mu2 = b >= NB ? mc : mr;
-    mu3 = b >= NB ? mr : mc;
+    mu2 = mir ? mc : mr;
+    mu3 = mir ? mr : mc;
     vi = g * xtile(NB, sizeof(CR)) + r * NB + cc;
   };
 #pragma unroll 1
   for (int i = lane; i < cnt; i += 64) {
     int mu2, mu3, vi;
-    decode(i, mu2, mu3, vi);
+    bool pair;
+    decode(i, mu2, mu3, vi, pair);
     const ModeRec<NT> p2 = load_rec<NB, NT>(c, a, mu2), p3 = load_rec<NB, NT>(c, a, mu3);
-    double dw, s2;
+    double dw, s2, dwm = 0.0;
     window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
+    if (CH == 1 && pair) {
+      // the mirrored member (lambda'' and lambda''' exchanged); its s2 equals s2 exactly
+      double s2m;
+      window_keep(add_signed(aw, p3.m.w, S2), p2.m.w, p3.m, p2.m, a.c_win, dwm, s2m);
+    }
     const CR vv = Xw[vi];
     const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
     const double sig2 = a.c_sig * s2;
-    double delta = 1.0;
+    double delta = (CH == 1 && pair) ? 2.0 : 1.0;
     if (!(sig2 < a.c_min)) {
       // adaptive Gaussian exp(-dw^2/sigma^2) / (sqrt(pi) sigma), 1/sqrt(pi) =
       // 0.5641895835477563; y = 1/sigma from the hardware reciprocal square root refined
@@ -438,6 +449,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
       y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
       delta = exp(-(dw * dw) * (y * y)) * (0.5641895835477563 * y);
+      if (CH == 1 && pair) delta += exp(-(dwm * dwm) * (y * y)) * (0.5641895835477563 * y);
     }
     const double base = kw * p2.iw * p3.iw * v2abs * delta;
 #pragma unroll
@@ -452,7 +464,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
         acc.r[CH][t] += base * f * invn[t];
       }
     }
-    acc.cnt[CH] += 1;
+    acc.cnt[CH] += (CH == 1 && pair) ? 2 : 1;
   }
 }
 
@@ -635,10 +647,15 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
       }
       if (act && r == 0) Gq[gw] = make_int2(iq2, iq3);
-      // place of the lane's kept processes in the wavefront's list: prefix sum of the
+      // the lane's list entries: single orientations, then mirror pairs with both kept
+      // (codes as in gamma_list); their place in the wavefront's list is a prefix sum of the
       // per-lane counts (<= 2 NB < 32) by bit-sliced ballots
-      const unsigned m = blk ? (bA | (bB << NB)) : 0u;
-      const int n = __popc(m);
+      const unsigned pr = bA & bB;
+      const unsigned long long m =
+          blk ? ((unsigned long long)(bA & ~pr) | ((unsigned long long)(bB & ~pr) << NB) |
+                 ((unsigned long long)pr << (2 * NB)))
+              : 0ull;
+      const int n = __popcll(m);
       int pre = 0, tot = 0;
 #pragma unroll
       for (int bsl = 0; bsl < 5; ++bsl) {
@@ -647,12 +664,12 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         tot += __popcll(bb) << bsl;
       }
       for (int base = 0; base < tot; base += LSEG) {
-        unsigned mm = m;
+        unsigned long long mm = m;
         int idx = pre;
         while (mm) {
-          const int b = __builtin_ctz(mm);
-          mm &= mm - 1u;
-          if (idx >= base && idx < base + LSEG) Lw[idx - base] = (unsigned short)((lane << 5) | b);
+          const int b = __builtin_ctzll(mm);
+          mm &= mm - 1ull;
+          if (idx >= base && idx < base + LSEG) Lw[idx - base] = (unsigned short)((lane << 6) | b);
           ++idx;
         }
         wave_sync();
