@@ -43,7 +43,7 @@ PEAK_FP32_VALU = 157.3e12
 # HBM bytes of one FP64 k_rates launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, each scaled by the counter's reading for a plain kernel that reads and
 # writes 256 MiB; valid only for the kernel sources they were taken with.
-TRAFFIC_FP64 = {"sources_sha256_16": "f8b63a8347f4231e", "bytes": 3.641e8 + 2.055e8}
+TRAFFIC_FP64 = {"sources_sha256_16": "b44cb1cb569feb6d", "bytes": 3.657e8 + 4.270e8}
 
 
 def kernel_sources_hash():
@@ -64,13 +64,16 @@ def kernel_sources_hash():
 def algorithmic_flops(stats, inst, n_pairs):
     """Algorithmic FLOPs of one main-kernel launch, the cheapest grouping of the arithmetic:
     W'' build 456 per combo per (lambda, lambda') pair, branch block 72 ng + 16 nb^3 per
-    contracted block, Gamma 40 + 6 nT per kept process (the per-candidate window test is
-    not credited)."""
+    contracted block, Gamma 40 + 6 nT per kept process of ++ and --, and for +- per mirror
+    pair 40 + 6 nT + 13 (the second member's dw and Gaussian), counting every +- process as a
+    pair member, which slightly undercounts (the per-candidate window test is not
+    credited)."""
     ng, nc, nb = inst["ng"], inst["nc"], inst["nb"]
     nT = inst["nT"]
+    g = 40.0 + 6.0 * nT
     return (456.0 * nc * n_pairs
             + (72.0 * ng + 16.0 * nb ** 3) * stats["blocks"]
-            + (40.0 + 6.0 * nT) * stats["processes"])
+            + g * stats["processes_pp_mm"] + (g + 13.0) * 0.5 * stats["processes_pm"])
 
 
 def groups_and_combos(fc4):
@@ -476,7 +479,9 @@ def main():
     nch = bin(inst.mask).count("1")
     # per active target: active lambda' x (N q'' x nb j'') x nb j''' per channel
     candidates = act * act * inst.nq * inst.nb * inst.nb * nch
-    stats = {"processes": processes, "candidates": candidates}
+    stats = {"processes": processes, "candidates": candidates,
+             "processes_pp_mm": int(counts[:, 0].sum() + counts[:, 2].sum()),
+             "processes_pm": int(counts[:, 1].sum())}
     lib_stats = ctx.last_stats()
     stats["blocks"] = lib_stats["blocks"]
     n_pairs = act * act
