@@ -209,8 +209,9 @@ int fp4_surrogate_features(fp4_ctx *ctx, const double *T, int32_t nT, double sca
 /* ---------------------------------------------------------------- batched instances
  * Several crystals (uneven branch counts, grids, quartet lists) evaluated by one captured HIP
  * graph: per instance occupations and precontraction, one persistent kernel per branch-count
- * class whose work-groups take (instance, target, q'-chunk) items from a global atomic
- * counter until it passes the total, per instance ordered reduction.  The graph is captured
+ * class whose work-groups take (instance, target, q'-chunk) items from atomic work queues
+ * (one per XCD range of the item list; a work-group drains its own XCD's range, then helps
+ * the others), per instance ordered reduction.  The graph is captured
  * on the first call and replayed while the instance buffers are unchanged; temperatures are
  * read from device memory at replay time. */
 
@@ -229,8 +230,8 @@ int fp4_batch_add(fp4_batch *b, fp4_ctx *ctx);
  *   rates   host, concatenated in the order of fp4_batch_add: for instance i a block
  *           [nT][nq_i*nb_i] (1/ps)
  *   counts  host, concatenated blocks [nq_i*nb_i][3], or NULL
- * Each instance uses its context's q'-chunk (FP4_PARAM_QCHUNK or fp4_autotune), 16 if
- * unset.  Synchronous. */
+ * Each instance uses its context's q'-chunk (FP4_PARAM_QCHUNK or fp4_autotune), or the
+ * automatic choice of a single call (at most 16) if unset.  Synchronous. */
 int fp4_batch_compute(fp4_batch *b, const double *T, int32_t nT, double scalebroad,
                       uint32_t mask, int32_t precision, double *rates, int64_t *counts);
 
