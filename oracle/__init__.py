@@ -40,6 +40,9 @@ def lib():
         L.oracle_rates4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32, f64,
                                     f64, f64, i32, P, i32, P, P, P, i32]
         L.oracle_rates4.restype = ctypes.c_int
+        L.oracle_rates4_class.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32,
+                                          f64, f64, f64, i32, P, P, i32, i32, P, P, P, i32]
+        L.oracle_rates4_class.restype = ctypes.c_int
         L.oracle_rates4_partners.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32,
                                              f64, f64, f64, i32, P, i32, P, i32, P, P, P, i32]
         L.oracle_rates4_partners.restype = ctypes.c_int
@@ -120,6 +123,29 @@ def rates4(model: Model, T, scalebroad, mask, dq, targets=None, window_w=2.0,
                              int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle_rates4 returned {rc}")
+    return rates, rch, counts
+
+
+def rates4_class(model: Model, A, qclass, T, scalebroad, mask, dq, targets=None,
+                 window_w=2.0, sigma_min=1e-4, want_rates=True, nthreads=0):
+    """The rate sum restricted to normal (qclass 1, Q = 0) or Umklapp (qclass 2, Q != 0)
+    processes, Q from the first-zone images of the four points (A: lattice vectors as rows).
+    Returns (rates[nT][nt], rates_ch[nT][3][nt], counts[nt][3])."""
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    if targets is None:
+        targets = np.arange(model.nq * model.nb)
+    targets = np.ascontiguousarray(targets, dtype=np.int32)
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+    nt = int(targets.shape[0])
+    rates = np.zeros((len(T), nt))
+    rch = np.zeros((len(T), 3, nt))
+    counts = np.zeros((nt, 3), dtype=np.int64)
+    rc = lib().oracle_rates4_class(*model._common(), _p(T), len(T), float(scalebroad), int(mask),
+                                   float(window_w), float(sigma_min), float(dq), nt,
+                                   _p(targets), _p(A), int(qclass), 1 if want_rates else 0,
+                                   _p(rates), _p(rch), _p(counts), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_rates4_class returned {rc}")
     return rates, rch, counts
 
 

@@ -150,6 +150,45 @@ static int fold(const model_t *m, int iq, int s1, int iq1, int s2, int iq2) {
     return r[0] + m->g[0] * (r[1] + m->g[1] * r[2]);
 }
 
+/* Reciprocal vectors as rows of B (2 pi included): B = 2 pi inv(A)^T, A rows = lattice
+ * vectors. */
+static void recip(const double A[9], double B[9]) {
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    /* row i of B is 2 pi (a_j x a_k) / det for (i, j, k) cyclic */
+    const double *a0 = A, *a1 = A + 3, *a2 = A + 6;
+    const double *r[3][2] = {{a1, a2}, {a2, a0}, {a0, a1}};
+    for (int i = 0; i < 3; ++i) {
+        const double *u = r[i][0], *v = r[i][1];
+        B[3 * i + 0] = 2.0 * M_PI * (u[1] * v[2] - u[2] * v[1]) / det;
+        B[3 * i + 1] = 2.0 * M_PI * (u[2] * v[0] - u[0] * v[2]) / det;
+        B[3 * i + 2] = 2.0 * M_PI * (u[0] * v[1] - u[1] * v[0]) / det;
+    }
+}
+
+/* First-Brillouin-zone image of grid point iq: the vector sum_d (n_d / N_d + m_d) b_d of
+ * smallest length over the integer shifts m_d in -2..1; among lengths equal within a
+ * relative 1e-10 the first shift in the order m1, m2, m3 (m1 slowest) is kept. */
+static void first_zone(const model_t *m, const double B[9], int iq, double k[3]) {
+    int n[3]; qtriple(m, iq, n);
+    double best = -1.0;
+    for (int m1 = -2; m1 <= 1; ++m1)
+        for (int m2 = -2; m2 <= 1; ++m2)
+            for (int m3 = -2; m3 <= 1; ++m3) {
+                const double f[3] = {(double)n[0] / m->g[0] + m1, (double)n[1] / m->g[1] + m2,
+                                     (double)n[2] / m->g[2] + m3};
+                double c[3], l2 = 0.0;
+                for (int x = 0; x < 3; ++x) {
+                    c[x] = f[0] * B[x] + f[1] * B[3 + x] + f[2] * B[6 + x];
+                    l2 += c[x] * c[x];
+                }
+                if (best < 0.0 || l2 < best * (1.0 - 1e-10)) {
+                    best = l2;
+                    k[0] = c[0]; k[1] = c[1]; k[2] = c[2];
+                }
+            }
+}
+
 /* exp(i q.R) for grid point iq and integer cell R (lattice coordinates). */
 static cplx phase(const model_t *m, int iq, const int32_t *R) {
     int n[3]; qtriple(m, iq, n);
@@ -265,6 +304,7 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
                       const double *T, int32_t nT, double scalebroad, uint32_t mask,
                       double window_w, double sigma_min, double dq, int32_t ntargets,
                       const int32_t *targets, int32_t nq1, const int32_t *q1list,
+                      const double *A, int32_t qclass,
                       int32_t want_rates, double *rates, double *rates_ch, int64_t *counts,
                       int32_t nthreads);
 
@@ -277,7 +317,27 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
                   double *rates_ch, int64_t *counts, int32_t nthreads) {
     return rates_core(grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi, T, nT,
                       scalebroad, mask, window_w, sigma_min, dq, ntargets, targets, -1, NULL,
-                      want_rates, rates, rates_ch, counts, nthreads);
+                      NULL, 0, want_rates, rates, rates_ch, counts, nthreads);
+}
+
+/* Public: the same sum restricted to normal processes (qclass 1: Q = 0) or to Umklapp
+ * processes (qclass 2: Q != 0), the two classes named after Eq. tao0.  Q is
+ * k(q''') - (k(q) + s' k(q') + s'' k(q'')) with k(q) the first-Brillouin-zone image of each
+ * grid point (the Cartesian image of smallest length; among images of equal length within a
+ * relative 1e-10, the first in the order of the integer shift m = (m1, m2, m3), each from
+ * -2 to 1, m1 slowest).  A[9]: lattice vectors as rows (Angstrom). */
+int oracle_rates4_class(const int32_t grid[3], int32_t natoms, const double *mass,
+                        const double *omega, const double *evec, const double *vel,
+                        int32_t nq4, const int32_t *atoms, const int32_t *cells,
+                        const double *phi, const double *T, int32_t nT, double scalebroad,
+                        uint32_t mask, double window_w, double sigma_min, double dq,
+                        int32_t ntargets, const int32_t *targets, const double *A,
+                        int32_t qclass, int32_t want_rates, double *rates, double *rates_ch,
+                        int64_t *counts, int32_t nthreads) {
+    if (!A || qclass < 0 || qclass > 2) return -1;
+    return rates_core(grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi, T, nT,
+                      scalebroad, mask, window_w, sigma_min, dq, ntargets, targets, -1, NULL,
+                      A, qclass, want_rates, rates, rates_ch, counts, nthreads);
 }
 
 /* Public: the same sum restricted to the partner points q' listed in q1list[nq1] (a sample of
@@ -295,7 +355,7 @@ int oracle_rates4_partners(const int32_t grid[3], int32_t natoms, const double *
         if (q1list[i] < 0 || q1list[i] >= grid[0] * grid[1] * grid[2]) return -1;
     return rates_core(grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi, T, nT,
                       scalebroad, mask, window_w, sigma_min, dq, ntargets, targets, nq1, q1list,
-                      want_rates, rates, rates_ch, counts, nthreads);
+                      NULL, 0, want_rates, rates, rates_ch, counts, nthreads);
 }
 
 static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
@@ -304,12 +364,20 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
                       const double *T, int32_t nT, double scalebroad, uint32_t mask,
                       double window_w, double sigma_min, double dq, int32_t ntargets,
                       const int32_t *targets, int32_t nq1, const int32_t *q1list,
+                      const double *A, int32_t qclass,
                       int32_t want_rates, double *rates, double *rates_ch, int64_t *counts,
                       int32_t nthreads) {
     if (natoms <= 0 || nT <= 0 || ntargets < 0 || scalebroad <= 0.0 || dq <= 0.0) return -1;
     model_t m;
     model_init(&m, grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi);
     const int N = m.N, nb = m.nb, nmodes = N * nb;
+    /* first-zone Cartesian image of every grid point (only for a class-restricted sum) */
+    double *kimg = NULL, Bm[9];
+    if (qclass) {
+        recip(A, Bm);
+        kimg = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+        for (int iq = 0; iq < N; ++iq) first_zone(&m, Bm, iq, kimg + 3 * iq);
+    }
     const int NQ1 = q1list ? nq1 : N;   /* partner points q' in the sum */
     const double c_win = ((window_w * scalebroad) * dq) * ((window_w * scalebroad) * dq);
     const double c_sig = (scalebroad * dq) * (scalebroad * dq);
@@ -377,6 +445,18 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
                     }
                     for (int iq2 = 0; iq2 < N; ++iq2) {
                         const int iq3 = fold(&m, iq, s1, iq1, s2, iq2);
+                        if (qclass) {
+                            /* Q = k(q''') - (k(q) + s' k(q') + s'' k(q'')), Cartesian */
+                            double q2 = 0.0, bl = 0.0;
+                            for (int x = 0; x < 3; ++x) {
+                                const double Qx = kimg[3 * iq3 + x] - (kimg[3 * iq + x] + s1 * kimg[3 * iq1 + x] +
+                                                                      s2 * kimg[3 * iq2 + x]);
+                                q2 += Qx * Qx;
+                                bl += Bm[x] * Bm[x];
+                            }
+                            const int umklapp = q2 > 1e-12 * bl;
+                            if ((qclass == 1 && umklapp) || (qclass == 2 && !umklapp)) continue;
+                        }
                         /* slot-4 factors of this q''' for each j''' (formed on first use) */
                         memset(have4, 0, sizeof(int) * (size_t)nb);
                         for (int j2 = 0; j2 < nb; ++j2) {
@@ -457,7 +537,7 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
             for (int ch = 0; ch < 3; ++ch) cc[ch] += pcnt[((size_t)it * NQ1 + k1) * 3 + ch];
         if (counts) for (int ch = 0; ch < 3; ++ch) counts[3 * (size_t)it + ch] = cc[ch];
     }
-    free(part); free(pcnt); free(occ);
+    free(part); free(pcnt); free(occ); free(kimg);
     model_free(&m);
     return 0;
 }

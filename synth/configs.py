@@ -122,6 +122,16 @@ def one_atom(seed: int = 45, grid=(4, 4, 4)) -> Instance:
                     fc, [300.0, 700.0])
 
 
+def ortho(seed: int = 46, grid=(4, 3, 2)) -> Instance:
+    cr = cx.ortho_one_atom()
+    rng = np.random.default_rng(seed)
+    fc2 = bvk_fc2(cr, [(3.0, 10.0), (3.3, 8.0), (3.6, 6.0)], rng)
+    om, ev, ve = modes(cr, fc2, tuple(grid))
+    fc = random_fc4(cr, 3.65, np.random.default_rng(seed + 1000))
+    return Instance(f"ortho-one-atom-{grid[0]}x{grid[1]}x{grid[2]}", cr, tuple(grid), om, ev, ve,
+                    fc, [300.0, 700.0])
+
+
 def cubic10(seed: int = 41) -> Instance:
     inst = diamond_instance((10, 10, 10), RC_SECOND, seed, (300.0, 700.0), 1.0, 7, "cubic-10x10x10")
     return inst

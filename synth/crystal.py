@@ -140,6 +140,14 @@ def fcc_one_atom(a: float = 3.6, mass: float = 63.5) -> Crystal:
                    [(np.eye(3), np.zeros(3))])
 
 
+def ortho_one_atom(a=(3.0, 3.3, 3.6), mass: float = 40.0) -> Crystal:
+    """One-atom simple orthorhombic cell (3 branches): orthogonal lattice vectors, so the
+    first-Brillouin-zone image of a grid point splits axis by axis.  Only the identity is
+    used as a symmetry operation."""
+    return Crystal("ortho_one_atom", np.diag(np.asarray(a, dtype=float)), np.zeros((1, 3)),
+                   np.array([mass]), [(np.eye(3), np.zeros(3))])
+
+
 def check_ops(cr: Crystal, tol: float = 1e-8) -> None:
     """Assert every stored operation maps every site onto a site."""
     for T, t in cr.ops:
