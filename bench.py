@@ -21,6 +21,9 @@ against separate calls, with every rate compared to the FP64 path.
 ``--batched-small`` runs 28 small instances (24 diamond-structure cells on 2x2x2 .. 4x4x4
 grids and 4 three-atom cells) in one graph replay against one synchronous call each.
 
+``--umklapp`` splits the 8x8x8 rates into normal and Umklapp processes (two class-restricted
+calls beside the unrestricted one) and reports kernel times, counts and the Umklapp share.
+
 ``--large`` runs the 16x16x16 workload (24 576 modes) on a random subset of 512 target modes
 in FP64 and with the FP32 contraction, and in FP64 at scalebroad 0.1.
 """
@@ -315,6 +318,53 @@ def batched_small_main(args):
         c.close()
 
 
+def umklapp_main(args):
+    """Normal / Umklapp split of the 8x8x8 workload (FP64, T = 300, 1000 K): the
+    unrestricted call and the two class-restricted calls (FP4_PARAM_QCLASS 1 and 2), their
+    kernel times, process counts and Umklapp share, and the check that the classes add up."""
+    import synth
+    import paper_2104_04895_amd as fp4
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    inst = synth.medium()
+    ctx = fp4.Context(0)
+    ctx.load_instance(inst)
+    ctx.set_param(fp4.FP4_PARAM_PROFILE, 1)
+    res = {}
+    for name, cls in (("all", 0), ("normal", 1), ("umklapp", 2)):
+        ctx.set_param(fp4.FP4_PARAM_QCLASS, cls)
+        r, rch, cnt = ctx.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64, by_channel=True)
+        tm = ctx.last_timing()
+        res[name] = (r, rch, cnt, tm["ms_main"], ctx.last_stats()["blocks"])
+        log(f"{name}: kernel {tm['ms_main']:.0f} ms, {int(cnt.sum())} processes")
+    r, rch, cnt, ms, blk = res["all"]
+    rn, rchn, cntn, msn, blkn = res["normal"]
+    ru, rchu, cntu, msu, blku = res["umklapp"]
+    act = r > 0
+    share = np.zeros_like(r)
+    share[act] = ru[act] / r[act]
+    out = {
+        "metric": "normal/Umklapp split of the 4ph rates: kernel time per class and Umklapp share",
+        "value": float(ms / 1e3), "unit": "s (unrestricted FP64 kernel)", "n_gpus": 1,
+        "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "diamond-structure 2-atom cell, 8x8x8 grid (3072 modes), "
+                               "second-shell FC4, T=300,1000 K, scalebroad 1"},
+        "kernel_ms": {"all": ms, "normal": msn, "umklapp": msu},
+        "contracted_blocks": {"all": int(blk), "normal": int(blkn), "umklapp": int(blku)},
+        "processes": {"all": int(cnt.sum()), "normal": int(cntn.sum()), "umklapp": int(cntu.sum())},
+        "processes_by_channel": {"normal": [int(x) for x in cntn.sum(0)],
+                                 "umklapp": [int(x) for x in cntu.sum(0)]},
+        "umklapp_share_of_rate": {"median": float(np.median(share[act])),
+                                  "min": float(share[act].min()), "max": float(share[act].max())},
+        "classes_add_up": {"counts_exact": bool(np.array_equal(cntn + cntu, cnt)),
+                           "max_rel_diff_rates": float(np.max(np.abs(rn + ru - r)[act] / r[act]))},
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
 def large_main(args):
     """16x16x16 grid (24 576 modes), second-shell FC4, T = 300 K: a seeded random subset of
     512 target modes in FP64 and with the FP32 contraction, every rate of the FP32 path
@@ -394,6 +444,8 @@ def main():
                     help="run the batched uneven-instance workload (one graph-captured launch)")
     ap.add_argument("--batched-small", action="store_true",
                     help="run the many-small-instances batched workload")
+    ap.add_argument("--umklapp", action="store_true",
+                    help="normal / Umklapp split of the 8x8x8 workload")
     ap.add_argument("--train-grid", type=int, default=12)
     ap.add_argument("--infer-grid", type=int, default=20)
     ap.add_argument("--draws", type=int, default=8)
@@ -417,6 +469,9 @@ def main():
         return
     if args.batched_small:
         batched_small_main(args)
+        return
+    if args.umklapp:
+        umklapp_main(args)
         return
     if args.large:
         large_main(args)

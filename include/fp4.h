@@ -57,6 +57,13 @@ extern "C" {
 #define FP4_PARAM_SIGMA_MIN 2     /* sigma below which delta := 1, rad/ps (default 1e-4) */
 #define FP4_PARAM_QCHUNK 3        /* q' points per work-group (0 = automatic) */
 #define FP4_PARAM_PROFILE 4       /* 1: time every kernel with HIP events (fp4_last_timing) */
+#define FP4_PARAM_QCLASS 5        /* processes summed: 0 all (default), 1 normal only (Q = 0),
+                                     2 Umklapp only (Q != 0), the classes named after Eq. tao0.
+                                     Q = k(q''') - (k(q) + s' k(q') + s'' k(q'')) with k the
+                                     first-zone image of a grid point: the shortest of
+                                     sum_d (n_d/N_d + m_d) b_d over m_d in -2..1, ties (relative
+                                     1e-10) to the first m in the order m1, m2, m3.  Rates and
+                                     counts of compute calls are then those of the class. */
 
 /* channel bits of the process mask (Eq. 4phgamma): recombination, redistribution, splitting */
 /* number of surrogate input features per (temperature, mode) row */

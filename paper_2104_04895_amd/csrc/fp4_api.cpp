@@ -89,7 +89,9 @@ struct fp4_ctx {
 
   // device buffers
   DevBuf d_omega, d_iw, d_m4, d_qbnd, d_vel, d_evec, d_mass, d_E64, d_E32, d_qn, d_PHA64, d_PHB64, d_PHD64, d_PHD32;
-  DevBuf d_qord, d_qordw;
+  DevBuf d_qord, d_qordw, d_qimg;
+  std::vector<int> h_qimg;
+  int qclass = 0;
   double w_lo = 0.0, w_hi = 0.0, v_hi = 0.0;
   DevBuf d_g_d, d_kl, d_cs, d_cj, d_ca, d_cq, d_qi, d_qb, d_qphi, d_avec, d_bvec, d_dvec;
   DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
@@ -178,6 +180,7 @@ fp4::Crystal make_crystal(const fp4_ctx *ctx) {
   c.vel = (const double4 *)ctx->d_vel.p;
   c.mode4 = (const double4 *)ctx->d_m4.p;
   c.qbound = (const double4 *)ctx->d_qbnd.p;
+  c.qimg = (const int4 *)ctx->d_qimg.p;
   c.qord = (const int4 *)ctx->d_qord.p;
   c.qord_w = (const double *)ctx->d_qordw.p;
   c.w_lo = ctx->w_lo;
@@ -251,6 +254,45 @@ int ensure_tables(fp4_ctx *ctx) {
     ctx->w_lo = wlo;
     ctx->w_hi = whi;
     ctx->v_hi = vhi;
+    // first-zone image of every grid point (normal / Umklapp classes): the shift m in
+    // {-2..1}^3 of smallest |sum_d (n_d/N_d + m_d) b_d|, ties (relative 1e-10) to the first m
+    // in the order m1, m2, m3
+    {
+      double Bv[9];
+      const double *a0 = ctx->A, *a1 = ctx->A + 3, *a2 = ctx->A + 6;
+      const double det = a0[0] * (a1[1] * a2[2] - a1[2] * a2[1]) - a0[1] * (a1[0] * a2[2] - a1[2] * a2[0]) +
+                         a0[2] * (a1[0] * a2[1] - a1[1] * a2[0]);
+      const double *pr[3][2] = {{a1, a2}, {a2, a0}, {a0, a1}};
+      for (int i = 0; i < 3; ++i) {
+        const double *u = pr[i][0], *v = pr[i][1];
+        Bv[3 * i + 0] = 2.0 * M_PI * (u[1] * v[2] - u[2] * v[1]) / det;
+        Bv[3 * i + 1] = 2.0 * M_PI * (u[2] * v[0] - u[0] * v[2]) / det;
+        Bv[3 * i + 2] = 2.0 * M_PI * (u[0] * v[1] - u[1] * v[0]) / det;
+      }
+      const int *g = ctx->grid;
+      ctx->h_qimg.assign(4 * N, 0);
+      for (size_t iq = 0; iq < N; ++iq) {
+        const int n[3] = {(int)(iq % g[0]), (int)((iq / g[0]) % g[1]), (int)(iq / ((size_t)g[0] * g[1]))};
+        double best = -1.0;
+        int bm[3] = {0, 0, 0};
+        for (int m1 = -2; m1 <= 1; ++m1)
+          for (int m2 = -2; m2 <= 1; ++m2)
+            for (int m3 = -2; m3 <= 1; ++m3) {
+              const double f[3] = {(double)n[0] / g[0] + m1, (double)n[1] / g[1] + m2, (double)n[2] / g[2] + m3};
+              double l2 = 0.0;
+              for (int x = 0; x < 3; ++x) {
+                const double cx = f[0] * Bv[x] + f[1] * Bv[3 + x] + f[2] * Bv[6 + x];
+                l2 += cx * cx;
+              }
+              if (best < 0.0 || l2 < best * (1.0 - 1e-10)) {
+                best = l2;
+                bm[0] = m1; bm[1] = m2; bm[2] = m3;
+              }
+            }
+        for (int d = 0; d < 3; ++d) ctx->h_qimg[4 * iq + d] = n[d] + bm[d] * g[d];
+      }
+      if ((rc = upload(ctx, ctx->d_qimg, ctx->h_qimg.data(), ctx->h_qimg.size()))) return rc;
+    }
     if ((rc = upload(ctx, ctx->d_qord, ctx->h_qord.data(), ctx->h_qord.size()))) return rc;
     if ((rc = upload(ctx, ctx->d_qordw, ctx->h_qordw.data(), ctx->h_qordw.size()))) return rc;
     FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -325,6 +367,7 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
   a.kpref = c4_prefactor() / ((double)ctx->N * (double)ctx->N);
   a.nT = nT;
   a.mask = mask;
+  a.qclass = ctx->qclass;
   a.occ = (const double *)ctx->d_occ.p;
   a.inv_occ = (const double *)ctx->d_iocc.p;
   a.qchunk = qchunk;
@@ -501,7 +544,7 @@ void fp4_destroy(fp4_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_qbnd, &ctx->d_qord, &ctx->d_qordw, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
+  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_qbnd, &ctx->d_qord, &ctx->d_qordw, &ctx->d_qimg, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
                    &ctx->d_E32, &ctx->d_qn, &ctx->d_PHA64, &ctx->d_PHB64, &ctx->d_PHD64,
                    &ctx->d_PHD32, &ctx->d_g_d, &ctx->d_kl, &ctx->d_cs, &ctx->d_cj, &ctx->d_ca,
                    &ctx->d_cq, &ctx->d_qi, &ctx->d_qb, &ctx->d_qphi, &ctx->d_avec, &ctx->d_bvec,
@@ -725,6 +768,11 @@ int fp4_set_param(fp4_ctx *ctx, int32_t key, double value) {
       return FP4_OK;
     case FP4_PARAM_PROFILE:
       ctx->profile = value != 0.0;
+      return FP4_OK;
+    case FP4_PARAM_QCLASS:
+      if (!(value == 0.0 || value == 1.0 || value == 2.0))
+        return ctx->fail(FP4_E_INVAL, "process class must be 0 (all), 1 (normal) or 2 (Umklapp)");
+      ctx->qclass = (int)value;
       return FP4_OK;
     default:
       return ctx->fail(FP4_E_INVAL, "unknown parameter key");
@@ -1173,6 +1221,7 @@ int prepare_instance(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t 
   a.kpref = c4_prefactor() / ((double)ctx->N * (double)ctx->N);
   a.nT = nT;
   a.mask = mask;
+  a.qclass = ctx->qclass;
   a.occ = (const double *)ctx->d_occ.p;
   a.inv_occ = (const double *)ctx->d_iocc.p;
   a.targets = (const int *)ctx->d_targets.p;

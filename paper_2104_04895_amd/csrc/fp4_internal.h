@@ -25,6 +25,7 @@ struct Crystal {
   const double4 *vel;       // [N*nb] (x, y, z, 0)
   const double4 *mode4;     // [N*nb] (vx, vy, vz, omega)
   const double4 *qbound;    // [N] (min omega, max omega, max |v|, 0) of the active branches
+  const int4 *qimg;         // [N] first-zone image of each q: n_d + m_d N_d per axis
   const int4 *qord;         // [N] (iq, n1, n2, n3) of the q points in ascending qbound.x
   const double *qord_w;     // [N] qbound.x in that order
   double w_lo, w_hi, v_hi;  // lowest and highest active frequency, highest speed
@@ -55,6 +56,7 @@ struct RateArgs {
   double kpref;             // C4 / N^2
   int nT;
   uint32_t mask;            // channel bits
+  int qclass;               // 0 all processes, 1 normal only (Q = 0), 2 Umklapp only
   const double *occ;        // [nT][N*nb]  n0 (0 for inactive modes)
   const double *inv_occ;    // [nT][N*nb]  1/n0 = expm1(hbar w / kT)
   const int *targets;       // [nt] mode ids

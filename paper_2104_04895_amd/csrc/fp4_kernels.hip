@@ -637,6 +637,18 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       if (act)
         row_bits_cols<NB, S2>(a, aw, c.mode4[iq2 * NB + r], c.qbound[iq3],
                               reinterpret_cast<const double2 *>(Xg), MIRROR && iq2 != iq3, bA, bB);
+      if (a.qclass != 0 && act) {
+        // normal / Umklapp class of the block (the same for every branch and, for a mirror
+        // pair, both orientations): Q = k(q''') - (k(q) + s' k(q') + s'' k(q'')) on the
+        // first-zone image numerators of the four points
+        const int4 k0 = c.qimg[mu / NB], k1 = c.qimg[mu1 / NB], k2 = c.qimg[iq2], k3 = c.qimg[iq3];
+        const bool umk = (k0.x + S1 * k1.x + S2 * k2.x != k3.x) || (k0.y + S1 * k1.y + S2 * k2.y != k3.y) ||
+                         (k0.z + S1 * k1.z + S2 * k2.z != k3.z);
+        if (umk != (a.qclass == 2)) {
+          bA = 0u;
+          bB = 0u;
+        }
+      }
       const unsigned long long bal = __ballot((bA | bB) != 0u);
       const bool blk = act && ((bal >> (gw * NB)) & GMASK) != 0ull;
       if (blk && r == 0) acc.blocks += 1;

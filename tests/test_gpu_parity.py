@@ -220,6 +220,36 @@ def test_async_on_caller_stream(fp4, small):
             assert _rel(rch.sum(axis=1), r) <= 1e-12
 
 
+def test_normal_umklapp_split(fp4):
+    """Rates restricted to normal or Umklapp processes (FP4_PARAM_QCLASS) against the
+    oracle's class sums on every mode of the 3x3x3 diamond workload and of a 4x3x2
+    orthorhombic one-atom cell: counts exact, FP64 rates within 1e-10, FP32 within 1e-4; the
+    two classes add up to the unrestricted call."""
+    from synth import configs
+    for inst in (synth.small(), configs.ortho()):
+        _say(f"case: normal/Umklapp split, {inst.name}")
+        m = oracle.Model.from_instance(inst)
+        dq = oracle.default_dq(inst.cr.A, inst.grid)
+        parts = []
+        with _ctx(fp4, inst) as c:
+            r_all, _, c_all = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+            for cls in (1, 2):
+                c.set_param(fp4.FP4_PARAM_QCLASS, cls)
+                r, _, cnt = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+                r32, _, cnt32 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP32)
+                r_o, _, c_o = oracle.rates4_class(m, inst.cr.A, cls, inst.T, 1.0, 7, dq)
+                assert c_o.sum() > 0
+                assert np.array_equal(cnt, c_o) and np.array_equal(cnt32, c_o)
+                assert _rel(r, r_o) <= RTOL64
+                assert _rel(r32, r_o) <= RTOL32
+                parts.append((r, cnt))
+            c.set_param(fp4.FP4_PARAM_QCLASS, 0)
+            r_back, _, _ = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+        assert np.array_equal(parts[0][1] + parts[1][1], c_all)
+        assert _rel(parts[0][0] + parts[1][0], r_all) <= 1e-12
+        assert np.array_equal(r_back, r_all)
+
+
 def test_properties_on_gpu(fp4, small):
     """Invariants that hold at any size, checked on the HIP path itself: time reversal
     (counts equal, rates equal to rounding), mask additivity, exact x4 under Phi -> 2 Phi."""
