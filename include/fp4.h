@@ -138,6 +138,26 @@ int fp4_compute_rates4_subset(fp4_ctx *ctx, const double *T, int32_t nT, double 
                               int32_t ntargets, double *rates, double *rates_by_channel,
                               int64_t *counts);
 
+/* Same on the irreducible part of the grid under a point group supplied by the caller.
+ *   rot [nrot][9] integer matrices (row-major) acting on reduced q coordinates,
+ *        q' = R q; in grid triples n'_d = sum_e R_de n_e N_d / N_e (mod N_d).  Every matrix
+ *        must map the grid onto itself (else FP4_E_INVAL); the caller includes the identity
+ *        and, for time reversal, -I.  1 <= nrot <= 96.
+ *   rates [nT][nq*nb] host; counts [nq*nb][3] host or NULL; *nirr (nullable) receives the
+ *        number of irreducible points.
+ * The grid points are split into orbits under the matrices; one representative per orbit
+ * (its lowest index) is computed with the full kernel; its rates are averaged over each set
+ * of degenerate branches (frequencies equal within 1e-9 relative) and copied, branch by
+ * branch, to every point of the orbit; counts are copied unaveraged.  Branches are matched by
+ * their order, so the frequencies at each q must be in ascending order; a point whose
+ * frequencies differ from its representative's (1e-8 relative) is reported as FP4_E_INVAL.
+ * Symmetry-equivalent modes have equal rates (and degenerate sets equal sums), so this
+ * equals the full-grid result averaged over degenerate branches, at a fraction of the
+ * cost.  Synchronous. */
+int fp4_compute_rates4_wedge(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                             uint32_t mask, int32_t precision, int32_t nrot, const int32_t *rot,
+                             double *rates, int64_t *counts, int32_t *nirr);
+
 /* Asynchronous form for callers that own the stream and the output memory.
  *   hip_stream   a hipStream_t of the context's device (NULL = the null stream)
  *   d_rates      DEVICE [nT][nq*nb] doubles (required)

@@ -42,7 +42,7 @@ EXPORTED = [
     "fp4_batch_last_error", "fp4_autotune", "fp4_mlp_create", "fp4_mlp_destroy",
     "fp4_mlp_last_error", "fp4_mlp_num_params", "fp4_mlp_get_params", "fp4_mlp_set_params",
     "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict", "fp4_load_fc3",
-    "fp4_compute_rates3", "fp4_surrogate_features",
+    "fp4_compute_rates3", "fp4_surrogate_features", "fp4_compute_rates4_wedge",
 ]
 FP4_NFEAT = 18
 
@@ -83,6 +83,7 @@ def lib():
         L.fp4_surrogate_features.argtypes = [P, P, i32, f64, P, i32, P, P, P, P]
         L.fp4_compute_rates4.argtypes = [P, P, i32, f64, u32, i32, P, P, P]
         L.fp4_compute_rates4_subset.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P]
+        L.fp4_compute_rates4_wedge.argtypes = [P, P, i32, f64, u32, i32, i32, P, P, P, P]
         L.fp4_compute_rates4_async.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
         L.fp4_debug_matrix_elements.argtypes = [P, i32, P, i32, P]
         L.fp4_last_stats.argtypes = [P, P, P, P]
@@ -252,6 +253,22 @@ class Context:
                                                    _p(rates), _p(rch), _p(cnt))
         self._check(rc, "fp4_compute_rates4")
         return rates, rch, cnt
+
+    def compute_rates4_wedge(self, T, scalebroad, mask, precision, rotations, counts=True):
+        """Rates on the irreducible grid points under integer rotations (reduced q
+        coordinates), averaged over degenerate branches and copied to every equivalent point.
+        Returns (rates[nT][nq*nb], counts[nq*nb][3] or None, number of irreducible points)."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        R = np.ascontiguousarray(rotations, dtype=np.int32).reshape(-1, 9)
+        nm = self.nq * self.nb
+        rates = np.zeros((len(T), nm))
+        cnt = np.zeros((nm, 3), dtype=np.int64) if counts else None
+        nirr = ctypes.c_int32()
+        self._check(self._L.fp4_compute_rates4_wedge(self._h, _p(T), len(T), float(scalebroad),
+                                                     int(mask), int(precision), len(R), _p(R),
+                                                     _p(rates), _p(cnt), ctypes.byref(nirr)),
+                    "fp4_compute_rates4_wedge")
+        return rates, cnt, nirr.value
 
     def compute_rates4_async(self, T, scalebroad, mask, precision, stream_ptr, d_rates,
                              d_rates_ch=0, d_counts=0):

@@ -807,6 +807,103 @@ int fp4_compute_rates4_subset(fp4_ctx *ctx, const double *T, int32_t nT, double 
   }
 }
 
+int fp4_compute_rates4_wedge(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                             uint32_t mask, int32_t precision, int32_t nrot, const int32_t *rot,
+                             double *rates, int64_t *counts, int32_t *nirr) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (!ctx->have_lattice || !ctx->have_modes || !ctx->have_fc4)
+      return ctx->fail(FP4_E_STATE, "compute called before fp4_load_lattice, fp4_load_modes and fp4_load_fc4");
+    if (nrot < 1 || nrot > 96 || !rot) return ctx->fail(FP4_E_INVAL, "need 1 <= nrot <= 96 rotations");
+    if (!rates) return ctx->fail(FP4_E_INVAL, "rates output is required");
+    (void)hipSetDevice(ctx->device);
+    const int N = ctx->N, nb = ctx->nb, nmodes = N * nb;
+    const int *g = ctx->grid;
+    // every rotation must map the grid onto itself: n'_d = sum_e R_de n_e N_d / N_e (mod N_d)
+    for (int k = 0; k < nrot; ++k)
+      for (int d = 0; d < 3; ++d)
+        for (int e = 0; e < 3; ++e) {
+          const long long r = rot[9 * k + 3 * d + e];
+          if (r != 0 && (r * g[d]) % g[e] != 0)
+            return ctx->fail(FP4_E_INVAL, "a rotation does not map the q-grid onto itself");
+        }
+    // orbits of the grid points under the rotations (union of the images), the lowest index
+    // of each orbit is its representative
+    std::vector<int> parent(N);
+    for (int i = 0; i < N; ++i) parent[i] = i;
+    auto find = [&](int i) {
+      while (parent[i] != i) i = parent[i] = parent[parent[i]];
+      return i;
+    };
+    for (int iq = 0; iq < N; ++iq) {
+      const int n[3] = {iq % g[0], (iq / g[0]) % g[1], iq / (g[0] * g[1])};
+      for (int k = 0; k < nrot; ++k) {
+        int m[3];
+        for (int d = 0; d < 3; ++d) {
+          long long acc = 0;
+          for (int e = 0; e < 3; ++e) acc += (long long)rot[9 * k + 3 * d + e] * n[e] * g[d] / g[e];
+          m[d] = (int)(((acc % g[d]) + g[d]) % g[d]);
+        }
+        const int jq = m[0] + g[0] * (m[1] + g[1] * m[2]);
+        int a = find(iq), b = find(jq);
+        if (a != b) parent[std::max(a, b)] = std::min(a, b);
+      }
+    }
+    std::vector<int> rep(N), reps;
+    for (int iq = 0; iq < N; ++iq) {
+      rep[iq] = find(iq);
+      if (rep[iq] == iq) reps.push_back(iq);
+    }
+    // the modes must be symmetric: the same (ascending-order) frequencies across an orbit
+    std::vector<double> w(nmodes);
+    FP4_HIP(ctx, hipMemcpy(w.data(), ctx->d_omega.p, nmodes * sizeof(double), hipMemcpyDeviceToHost));
+    for (int iq = 0; iq < N; ++iq)
+      for (int j = 0; j < nb; ++j) {
+        const double a = w[(size_t)iq * nb + j], b = w[(size_t)rep[iq] * nb + j];
+        if (std::fabs(a - b) > 1e-8 * std::max(std::fabs(a), std::fabs(b)) + 1e-12)
+          return ctx->fail(FP4_E_INVAL, "frequencies differ across a rotation orbit (not a symmetry of the modes)");
+      }
+    std::vector<int> tl;
+    for (int iq : reps)
+      for (int j = 0; j < nb; ++j) tl.push_back(iq * nb + j);
+    const int nt = (int)tl.size();
+    std::vector<double> r((size_t)nT * nt);
+    std::vector<int64_t> c((size_t)nt * 3);
+    int rc = compute_common(ctx, T, nT, scalebroad, mask, precision, tl.data(), nt, r.data(),
+                            nullptr, c.data());
+    if (rc) return rc;
+    // average over degenerate branches of each representative, then copy to its orbit
+    std::vector<int> slot(N, -1);
+    for (size_t k = 0; k < reps.size(); ++k) slot[reps[k]] = (int)k;
+    for (size_t k = 0; k < reps.size(); ++k) {
+      const double *wq = w.data() + (size_t)reps[k] * nb;
+      for (int j = 0; j < nb;) {
+        int e = j + 1;
+        while (e < nb && std::fabs(wq[e] - wq[j]) <= 1e-9 * std::max(std::fabs(wq[j]), 1e-30)) ++e;
+        for (int t = 0; t < nT; ++t) {
+          double sum = 0.0;
+          for (int i = j; i < e; ++i) sum += r[(size_t)t * nt + k * nb + i];
+          for (int i = j; i < e; ++i) r[(size_t)t * nt + k * nb + i] = sum / (e - j);
+        }
+        j = e;
+      }
+    }
+    for (int iq = 0; iq < N; ++iq) {
+      const size_t k = (size_t)slot[rep[iq]];
+      for (int j = 0; j < nb; ++j) {
+        for (int t = 0; t < nT; ++t) rates[(size_t)t * nmodes + (size_t)iq * nb + j] = r[(size_t)t * nt + k * nb + j];
+        if (counts)
+          for (int ch = 0; ch < 3; ++ch) counts[((size_t)iq * nb + j) * 3 + ch] = c[(k * nb + j) * 3 + ch];
+      }
+    }
+    if (nirr) *nirr = (int32_t)reps.size();
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
 int fp4_compute_rates4_async(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
                              uint32_t mask, int32_t precision, void *hip_stream,
                              double *d_rates, double *d_rates_by_channel, int64_t *d_counts) {

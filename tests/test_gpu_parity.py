@@ -250,6 +250,60 @@ def test_normal_umklapp_split(fp4):
         assert np.array_equal(r_back, r_all)
 
 
+def _lattice_rotations(cr):
+    """Integer matrices M = A T A^-1 of the crystal's point-group operations acting on reduced
+    q coordinates (q = B^T f with B = 2 pi inv(A)^T, so f' = A T inv(A) f)."""
+    A = np.asarray(cr.A, dtype=np.float64)
+    Ai = np.linalg.inv(A)
+    mats = []
+    for T, _ in cr.ops:
+        M = A @ np.asarray(T) @ Ai
+        Mi = np.rint(M)
+        assert np.max(np.abs(M - Mi)) < 1e-8
+        mats.append(Mi.astype(np.int32))
+    return np.unique(np.array(mats).reshape(-1, 9), axis=0)
+
+
+def _degenerate_average(r, omega, nb):
+    out = r.copy()
+    w = np.asarray(omega).reshape(-1, nb)
+    for iq in range(w.shape[0]):
+        j = 0
+        while j < nb:
+            e = j + 1
+            while e < nb and abs(w[iq, e] - w[iq, j]) <= 1e-9 * max(abs(w[iq, j]), 1e-30):
+                e += 1
+            out[:, iq * nb + j:iq * nb + e] = r[:, iq * nb + j:iq * nb + e].mean(axis=1, keepdims=True)
+            j = e
+    return out
+
+
+def test_irreducible_wedge(fp4, small):
+    """fp4_compute_rates4_wedge with the 48 point-group matrices of the diamond structure: only
+    the irreducible points of the 3x3x3 grid are computed, and every rate equals the oracle's
+    full-grid rate averaged over degenerate branches (1e-10); a matrix that does not map a
+    3x3x2 grid onto itself is rejected."""
+    _say("case: irreducible wedge, 3x3x3 diamond")
+    rots = _lattice_rotations(small.cr)
+    assert len(rots) == 48
+    r_o, _, _ = _oracle(small, small.T, 1.0, 7)
+    ref = _degenerate_average(r_o, small.omega, small.nb)
+    with _ctx(fp4, small) as c:
+        r, cnt, nirr = c.compute_rates4_wedge(small.T, 1.0, 7, fp4.FP4_FP64, rots)
+        r32, _, _ = c.compute_rates4_wedge(small.T, 1.0, 7, fp4.FP4_FP32, rots)
+    assert 1 < nirr < small.nq
+    assert _rel(r, ref) <= RTOL64
+    assert _rel(r32, ref) <= RTOL32
+    inst = synth.diamond_instance((3, 3, 2), synth.configs.RC_FIRST, 5)
+    swap = np.array([[0, 0, 1], [0, 1, 0], [1, 0, 0]], dtype=np.int32).reshape(1, 9)
+    with _ctx(fp4, inst) as c:
+        T = np.array([300.0])
+        out = np.zeros(inst.nmodes)
+        rc = c.call("fp4_compute_rates4_wedge", T.ctypes.data, 1, 1.0, 7, 0, 1, swap.ctypes.data,
+                    out.ctypes.data, None, None)
+        assert rc == fp4.FP4_E_INVAL
+
+
 def test_properties_on_gpu(fp4, small):
     """Invariants that hold at any size, checked on the HIP path itself: time reversal
     (counts equal, rates equal to rounding), mask additivity, exact x4 under Phi -> 2 Phi."""
