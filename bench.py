@@ -49,7 +49,7 @@ PEAK_FP32_VALU = 157.3e12
 # HBM bytes of one FP64 k_rates launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, each scaled by the counter's reading for a plain kernel that reads and
 # writes 256 MiB; valid only for the kernel sources they were taken with.
-TRAFFIC_FP64 = {"sources_sha256_16": "b44cb1cb569feb6d", "bytes": 3.657e8 + 4.270e8}
+TRAFFIC_FP64 = {"sources_sha256_16": "c8486118afa3a515", "bytes": 3.657e8 + 4.116e8}
 
 
 def kernel_sources_hash():
