@@ -51,6 +51,14 @@ PEAK_FP32_VALU = 157.3e12
 # writes 256 MiB; valid only for the kernel sources they were taken with.
 TRAFFIC_FP64 = {"sources_sha256_16": "c8486118afa3a515", "bytes": 3.657e8 + 4.116e8}
 
+# Wavefront VALU instructions of one FP64 k_rates launch on this workload (rocprofv3 --pmc
+# SQ_INSTS_VALU, and the FP64 FMA + MUL + ADD counters); valid only for the kernel sources
+# they were taken with.  The chip issues at most one wave64 FP64 VALU instruction per CU per
+# cycle: 256 CUs x 2.4 GHz.
+VALU_FP64 = {"sources_sha256_16": "c8486118afa3a515", "insts": 5.374e11,
+             "fp64_insts": 1.796e11 + 4.133e10 + 3.641e10}
+VALU_ISSUE_PER_S = 256 * 2.4e9
+
 
 def kernel_sources_hash():
     """sha256 (first 16 hex digits) of the rate kernel's sources with comments and blank
@@ -611,6 +619,11 @@ def main():
         "contracted_blocks_per_step": stats["blocks"],
         "hbm_gb_per_s": (traffic / t_main / 1e9) if traffic else None,
     }
+    if prec == fp4.FP4_FP64 and kernel_sources_hash() == VALU_FP64["sources_sha256_16"]:
+        extras["valu"] = {"insts_per_launch": VALU_FP64["insts"],
+                          "issue_frac": VALU_FP64["insts"] / (t_main * VALU_ISSUE_PER_S),
+                          "fp64_fma_mul_add_share": VALU_FP64["fp64_insts"] / VALU_FP64["insts"]}
+    extras["mfma_utilisation"] = 0.0   # the rate kernel has no dense contraction to put there
     # time to solution: the synchronous call, rates and counts copied back to the host
     t0 = time.perf_counter()
     ctx.compute_rates4(inst.T, inst.scalebroad, inst.mask, prec)
