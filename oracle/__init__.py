@@ -40,6 +40,9 @@ def lib():
         L.oracle_rates4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32, f64,
                                     f64, f64, i32, P, i32, P, P, P, i32]
         L.oracle_rates4.restype = ctypes.c_int
+        L.oracle_phase_space4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32,
+                                          f64, f64, f64, i32, P, i32, P, P, P, i32]
+        L.oracle_phase_space4.restype = ctypes.c_int
         L.oracle_rates4_class.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, i32, f64, u32,
                                           f64, f64, f64, i32, P, P, i32, i32, P, P, P, i32]
         L.oracle_rates4_class.restype = ctypes.c_int
@@ -124,6 +127,28 @@ def rates4(model: Model, T, scalebroad, mask, dq, targets=None, window_w=2.0,
     if rc != 0:
         raise ValueError(f"oracle_rates4 returned {rc}")
     return rates, rch, counts
+
+
+def phase_space4(model: Model, kind, T, scalebroad, mask, dq, targets=None, window_w=2.0,
+                 sigma_min=1e-4, nthreads=0):
+    """Four-phonon phase spaces (kind 1: weighted WP4, kind 2: P4), the rate sum with
+    |V|^2 and the prefactor set to 1.  Returns (values[nT][nt], by_channel[nT][3][nt],
+    counts[nt][3])."""
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    if targets is None:
+        targets = np.arange(model.nq * model.nb)
+    targets = np.ascontiguousarray(targets, dtype=np.int32)
+    nt = int(targets.shape[0])
+    out = np.zeros((len(T), nt))
+    och = np.zeros((len(T), 3, nt))
+    counts = np.zeros((nt, 3), dtype=np.int64)
+    rc = lib().oracle_phase_space4(*model._common(), _p(T), len(T), float(scalebroad), int(mask),
+                                   float(window_w), float(sigma_min), float(dq), nt,
+                                   _p(targets), int(kind), _p(out), _p(och), _p(counts),
+                                   int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_phase_space4 returned {rc}")
+    return out, och, counts
 
 
 def rates4_class(model: Model, A, qclass, T, scalebroad, mask, dq, targets=None,

@@ -320,6 +320,27 @@ int oracle_rates4(const int32_t grid[3], int32_t natoms, const double *mass,
                       NULL, 0, want_rates, rates, rates_ch, counts, nthreads);
 }
 
+/* Public: four-phonon phase spaces, the rate sum of Eq. tao0 with the anharmonic strength
+ * taken out (no force constants are used; the channel weights 1/2, 1/2, 1/6 and 1/N^2 stay):
+ *   kind 1, weighted phase space WP4: each process contributes its occupation factor of
+ *     Eq. 4phgamma (over n0_lambda) times delta / (w w' w'' w''')   [ps^5];
+ *   kind 2, phase space P4: each process contributes delta          [ps].
+ * The paper defines the weighting in a reference it cites without printing it; these are
+ * the Eq. 4phgamma terms with |V|^2 and the prefactor hbar^2 pi / 8 set to 1.  Outputs as
+ * for oracle_rates4 (counts are the same kept-process counts). */
+int oracle_phase_space4(const int32_t grid[3], int32_t natoms, const double *mass,
+                        const double *omega, const double *evec, const double *vel,
+                        int32_t nq4, const int32_t *atoms, const int32_t *cells,
+                        const double *phi, const double *T, int32_t nT, double scalebroad,
+                        uint32_t mask, double window_w, double sigma_min, double dq,
+                        int32_t ntargets, const int32_t *targets, int32_t kind, double *rates,
+                        double *rates_ch, int64_t *counts, int32_t nthreads) {
+    if (kind < 1 || kind > 2) return -1;
+    return rates_core(grid, natoms, mass, omega, evec, vel, nq4, atoms, cells, phi, T, nT,
+                      scalebroad, mask, window_w, sigma_min, dq, ntargets, targets, -1, NULL,
+                      NULL, 0, kind + 1, rates, rates_ch, counts, nthreads);
+}
+
 /* Public: the same sum restricted to normal processes (qclass 1: Q = 0) or to Umklapp
  * processes (qclass 2: Q != 0), the two classes named after Eq. tao0.  Q is
  * k(q''') - (k(q) + s' k(q') + s'' k(q'')) with k(q) the first-Brillouin-zone image of each
@@ -423,7 +444,7 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
                     if (omega[mu1] <= 0.0) continue;
                     /* slot-1 x slot-2 partial contraction per quartet:
                      * W_n^{gt} = sum_{ab} Phi_n^{abgt} X1_n^a X2_n^b */
-                    if (want_rates) {
+                    if (want_rates == 1) {
                         for (int n = 0; n < m.nq4; ++n) {
                             const int32_t *at = m.atoms + 4 * n;
                             const int32_t *cl = m.cells + 9 * n;
@@ -470,6 +491,8 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
                                 if (!keep_process(&m, ch, mu, mu1, mu2, mu3, c_win, &dw, &s2v)) continue;
                                 C[ch] += 1;
                                 if (!want_rates) continue;
+                                double v2 = 1.0;   /* phase-space sums: |V|^2 := 1 */
+                                if (want_rates == 1) {
                                 if (!have3) {
                                     for (int n = 0; n < m.nq4; ++n)
                                         for (int x = 0; x < 3; ++x)
@@ -491,7 +514,8 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
                                         for (int d = 0; d < 3; ++d) y += W[9 * n + 3 * c + d] * X4[3 * n + d];
                                         V += X3[3 * n + c] * y;
                                     }
-                                const double v2 = creal(V) * creal(V) + cimag(V) * cimag(V);
+                                v2 = creal(V) * creal(V) + cimag(V) * cimag(V);
+                                }
                                 const double delta = oracle_delta(dw, c_sig * s2v, sigma_min);
                                 const double wprod = omega[mu] * omega[mu1] * omega[mu2] * omega[mu3];
                                 for (int t = 0; t < nT; ++t) {
@@ -501,7 +525,9 @@ static int rates_core(const int32_t grid[3], int32_t natoms, const double *mass,
                                     if (ch == 0) f = (1.0 + n0[mu1]) * (1.0 + n0[mu2]) * n0[mu3] / n0[mu];
                                     else if (ch == 1) f = (1.0 + n0[mu1]) * n0[mu2] * n0[mu3] / n0[mu];
                                     else f = n0[mu1] * n0[mu2] * n0[mu3] / n0[mu];
-                                    const double G = C4 * inv_n2 * f * v2 * delta / wprod;
+                                    double G = C4 * inv_n2 * f * v2 * delta / wprod;
+                                    if (want_rates == 2) G = inv_n2 * f * delta / wprod;    /* WP4 */
+                                    else if (want_rates == 3) G = inv_n2 * delta;          /* P4 */
                                     neumaier(&P[(t * 3 + ch) * 2], &P[(t * 3 + ch) * 2 + 1], CH_W[ch] * G);
                                 }
                             }
