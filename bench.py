@@ -27,6 +27,9 @@ calls beside the unrestricted one) and reports kernel times, counts and the Umkl
 ``--wedge`` computes the 8x8x8 rates on the irreducible grid points under the diamond
 structure's 48 point-group operations and compares them with the full grid.
 
+``--phase-space`` computes the phase spaces P4 and WP4 (no force constants) of the 8x8x8
+workload and times them against the rates.
+
 ``--large`` runs the 16x16x16 workload (24 576 modes) on a random subset of 512 target modes
 in FP64 and with the FP32 contraction, and in FP64 at scalebroad 0.1.
 """
@@ -425,6 +428,41 @@ def wedge_main(args):
     ctx.close()
 
 
+def phase_space_main(args):
+    """Phase spaces of the 8x8x8 workload (no force constants used): P4 and WP4 with the
+    kept-process counts, timed against the rate call (the quick estimate of the cost of the
+    four-phonon sum the phase spaces serve for)."""
+    import synth
+    import paper_2104_04895_amd as fp4
+
+    inst = synth.medium()
+    ctx = fp4.Context(0)
+    ctx.load_instance(inst)
+    ctx.set_param(fp4.FP4_PARAM_PROFILE, 1)
+    res = {}
+    for name, kind in (("rates", 0), ("wp4", 1), ("p4", 2)):
+        ctx.set_param(fp4.FP4_PARAM_PHASE_SPACE, kind)
+        v, _, cnt = ctx.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+        res[name] = (v, cnt, ctx.last_timing()["ms_main"])
+        print(f"# {name}: kernel {res[name][2]:.0f} ms", file=sys.stderr, flush=True)
+    act = res["p4"][0][0] > 0
+    out = {
+        "metric": "four-phonon phase spaces P4 / WP4 and kept-process counts: kernel time against the rates",
+        "value": res["rates"][2] / res["p4"][2], "unit": "x (rate kernel ms / P4 kernel ms)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "diamond-structure 2-atom cell, 8x8x8 grid (3072 modes), "
+                               "T=300,1000 K, scalebroad 1 (no force constants used)"},
+        "kernel_ms": {k: res[k][2] for k in res},
+        "counts_equal_to_rates_call": bool(np.array_equal(res["p4"][1], res["rates"][1])
+                                          and np.array_equal(res["wp4"][1], res["rates"][1])),
+        "p4_ps": {"median": float(np.median(res["p4"][0][0][act])), "max": float(res["p4"][0][0].max())},
+        "wp4_300K_ps5": {"median": float(np.median(res["wp4"][0][0][act])),
+                         "max": float(res["wp4"][0][0].max())},
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
 def large_main(args):
     """16x16x16 grid (24 576 modes), second-shell FC4, T = 300 K: a seeded random subset of
     512 target modes in FP64 and with the FP32 contraction, every rate of the FP32 path
@@ -506,6 +544,8 @@ def main():
                     help="run the many-small-instances batched workload")
     ap.add_argument("--umklapp", action="store_true",
                     help="normal / Umklapp split of the 8x8x8 workload")
+    ap.add_argument("--phase-space", action="store_true",
+                    help="phase spaces P4 / WP4 of the 8x8x8 workload against the rates")
     ap.add_argument("--wedge", action="store_true",
                     help="8x8x8 workload on the irreducible grid points against the full grid")
     ap.add_argument("--train-grid", type=int, default=12)
@@ -537,6 +577,9 @@ def main():
         return
     if args.wedge:
         wedge_main(args)
+        return
+    if args.phase_space:
+        phase_space_main(args)
         return
     if args.large:
         large_main(args)

@@ -64,6 +64,15 @@ extern "C" {
                                      sum_d (n_d/N_d + m_d) b_d over m_d in -2..1, ties (relative
                                      1e-10) to the first m in the order m1, m2, m3.  Rates and
                                      counts of compute calls are then those of the class. */
+#define FP4_PARAM_PHASE_SPACE 6   /* 0 rates (default); otherwise compute calls return a
+                                     four-phonon phase space in place of the rates, with no
+                                     force constants used (|V|^2 := 1, no contraction):
+                                     1 weighted phase space WP4, each kept process weighted
+                                     like Eq. 4phgamma without |V|^2 and hbar^2 pi / 8
+                                     (occupation factor over n0_lambda, delta, 1/(w w' w'' w'''),
+                                     channel weight, 1/N^2; ps^5); 2 phase space P4, channel
+                                     weight times delta over N^2 (ps).  Counts are the kept
+                                     processes as for the rates. */
 
 /* channel bits of the process mask (Eq. 4phgamma): recombination, redistribution, splitting */
 /* number of surrogate input features per (temperature, mode) row */

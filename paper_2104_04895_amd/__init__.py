@@ -30,6 +30,7 @@ FP4_PARAM_SIGMA_MIN = 2
 FP4_PARAM_QCHUNK = 3
 FP4_PARAM_PROFILE = 4
 FP4_PARAM_QCLASS = 5
+FP4_PARAM_PHASE_SPACE = 6
 
 FP4_PP, FP4_PM, FP4_MM = 1, 2, 4
 

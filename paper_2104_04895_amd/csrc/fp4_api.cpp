@@ -91,7 +91,7 @@ struct fp4_ctx {
   DevBuf d_omega, d_iw, d_m4, d_qbnd, d_vel, d_evec, d_mass, d_E64, d_E32, d_qn, d_PHA64, d_PHB64, d_PHD64, d_PHD32;
   DevBuf d_qord, d_qordw, d_qimg;
   std::vector<int> h_qimg;
-  int qclass = 0;
+  int qclass = 0, harmonic = 0;
   double w_lo = 0.0, w_hi = 0.0, v_hi = 0.0;
   DevBuf d_g_d, d_kl, d_cs, d_cj, d_ca, d_cq, d_qi, d_qb, d_qphi, d_avec, d_bvec, d_dvec;
   DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
@@ -364,7 +364,8 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
   a.sqrt_c_win = wsb * ctx->dq;
   a.c_sig = (sb * ctx->dq) * (sb * ctx->dq);
   a.c_min = ctx->sigma_min * ctx->sigma_min;
-  a.kpref = c4_prefactor() / ((double)ctx->N * (double)ctx->N);
+  a.kpref = (ctx->harmonic ? 1.0 : c4_prefactor()) / ((double)ctx->N * (double)ctx->N);
+  a.harmonic = ctx->harmonic;
   a.nT = nT;
   a.mask = mask;
   a.qclass = ctx->qclass;
@@ -768,6 +769,11 @@ int fp4_set_param(fp4_ctx *ctx, int32_t key, double value) {
       return FP4_OK;
     case FP4_PARAM_PROFILE:
       ctx->profile = value != 0.0;
+      return FP4_OK;
+    case FP4_PARAM_PHASE_SPACE:
+      if (!(value == 0.0 || value == 1.0 || value == 2.0))
+        return ctx->fail(FP4_E_INVAL, "phase-space kind must be 0 (rates), 1 (WP4) or 2 (P4)");
+      ctx->harmonic = (int)value;
       return FP4_OK;
     case FP4_PARAM_QCLASS:
       if (!(value == 0.0 || value == 1.0 || value == 2.0))
@@ -1315,7 +1321,8 @@ int prepare_instance(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t 
   a.sqrt_c_win = wsb * ctx->dq;
   a.c_sig = (sb * ctx->dq) * (sb * ctx->dq);
   a.c_min = ctx->sigma_min * ctx->sigma_min;
-  a.kpref = c4_prefactor() / ((double)ctx->N * (double)ctx->N);
+  a.kpref = (ctx->harmonic ? 1.0 : c4_prefactor()) / ((double)ctx->N * (double)ctx->N);
+  a.harmonic = ctx->harmonic;
   a.nT = nT;
   a.mask = mask;
   a.qclass = ctx->qclass;

@@ -57,6 +57,7 @@ struct RateArgs {
   int nT;
   uint32_t mask;            // channel bits
   int qclass;               // 0 all processes, 1 normal only (Q = 0), 2 Umklapp only
+  int harmonic;             // 0 rates; phase spaces with |V|^2 := 1: 1 WP4, 2 P4
   const double *occ;        // [nT][N*nb]  n0 (0 for inactive modes)
   const double *inv_occ;    // [nT][N*nb]  1/n0 = expm1(hbar w / kT)
   const int *targets;       // [nt] mode ids

@@ -437,8 +437,11 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       double s2m;
       window_keep(add_signed(aw, p3.m.w, S2), p2.m.w, p3.m, p2.m, a.c_win, dwm, s2m);
     }
-    const CR vv = Xw[vi];
-    const double v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
+    double v2abs = 1.0;
+    if (a.harmonic == 0) {
+      const CR vv = Xw[vi];
+      v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
+    }
     const double sig2 = a.c_sig * s2;
     double delta = (CH == 1 && pair) ? 2.0 : 1.0;
     if (!(sig2 < a.c_min)) {
@@ -451,7 +454,9 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       delta = exp(-(dw * dw) * (y * y)) * (0.5641895835477563 * y);
       if (CH == 1 && pair) delta += exp(-(dwm * dwm) * (y * y)) * (0.5641895835477563 * y);
     }
-    const double base = kw * p2.iw * p3.iw * v2abs * delta;
+    // P4 (harmonic 2): channel weight / N^2 times delta only
+    const bool p4 = a.harmonic == 2;
+    const double base = p4 ? kw * delta : kw * p2.iw * p3.iw * v2abs * delta;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (t < a.nT) {
@@ -461,7 +466,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
         if (CH == 0) f = (1.0 + n1[t]) * (1.0 + n2) * n3;
         else if (CH == 1) f = (1.0 + n1[t]) * n2 * n3;
         else f = n1[t] * n2 * n3;
-        acc.r[CH][t] += base * f * invn[t];
+        acc.r[CH][t] += p4 ? base : base * f * invn[t];
       }
     }
     acc.cnt[CH] += (CH == 1 && pair) ? 2 : 1;
@@ -499,7 +504,8 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   const CR *Ws = W + (S1 > 0 ? 0 : c.ng * 9);
   const double aw = add_signed(w, w1, S1);
   // weight of the channel (Eq. tao0), prefactor C4/N^2 and 1/(w w') of Eq. 4phgamma
-  const double kw = WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
+  // (the phase space P4 keeps only the channel weight and 1/N^2)
+  const double kw = a.harmonic == 2 ? WCH * a.kpref : WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
   const unsigned long long lt = (1ull << lane) - 1ull;
   const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
   // ++ and --: q'' is scanned in ascending order of its lowest active frequency, and only as
@@ -652,7 +658,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       const unsigned long long bal = __ballot((bA | bB) != 0u);
       const bool blk = act && ((bal >> (gw * NB)) & GMASK) != 0ull;
       if (blk && r == 0) acc.blocks += 1;
-      if (blk) {
+      if (blk && a.harmonic == 0) {   // the phase spaces take |V|^2 := 1
         CR V[NB];
         block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
 #pragma unroll

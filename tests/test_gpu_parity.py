@@ -304,6 +304,29 @@ def test_irreducible_wedge(fp4, small):
         assert rc == fp4.FP4_E_INVAL
 
 
+def test_phase_spaces(fp4, small):
+    """FP4_PARAM_PHASE_SPACE 1 (weighted WP4) and 2 (P4) against the oracle's phase-space
+    sums on every mode of the 3x3x3 workload, FP64 and FP32 settings (no contraction runs, so
+    both are FP64 sums): counts exact, values within 1e-10; back to rates afterwards."""
+    _say("case: phase spaces, 3x3x3")
+    m = oracle.Model.from_instance(small)
+    dq = oracle.default_dq(small.cr.A, small.grid)
+    T = [300.0, 900.0]
+    with _ctx(fp4, small) as c:
+        r0, _, _ = c.compute_rates4(T, 1.0, 7, fp4.FP4_FP64)
+        for kind in (1, 2):
+            c.set_param(fp4.FP4_PARAM_PHASE_SPACE, kind)
+            v, _, cnt = c.compute_rates4(T, 1.0, 7, fp4.FP4_FP64)
+            v32, _, cnt32 = c.compute_rates4(T, 1.0, 7, fp4.FP4_FP32)
+            ref, _, cref = oracle.phase_space4(m, kind, T, 1.0, 7, dq)
+            assert cref.sum() > 0
+            assert np.array_equal(cnt, cref) and np.array_equal(cnt32, cref)
+            assert _rel(v, ref) <= RTOL64 and _rel(v32, ref) <= RTOL64
+        c.set_param(fp4.FP4_PARAM_PHASE_SPACE, 0)
+        r1, _, _ = c.compute_rates4(T, 1.0, 7, fp4.FP4_FP64)
+    assert np.array_equal(r0, r1)
+
+
 def test_properties_on_gpu(fp4, small):
     """Invariants that hold at any size, checked on the HIP path itself: time reversal
     (counts equal, rates equal to rounding), mask additivity, exact x4 under Phi -> 2 Phi."""
