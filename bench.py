@@ -52,14 +52,14 @@ PEAK_FP32_VALU = 157.3e12
 # HBM bytes of one FP64 k_rates launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, each scaled by the counter's reading for a plain kernel that reads and
 # writes 256 MiB; valid only for the kernel sources they were taken with.
-TRAFFIC_FP64 = {"sources_sha256_16": "c8486118afa3a515", "bytes": 3.657e8 + 4.116e8}
+TRAFFIC_FP64 = {"sources_sha256_16": "c786dc84f9a7d3dc", "bytes": 3.658e8 + 4.114e8}
 
 # Wavefront VALU instructions of one FP64 k_rates launch on this workload (rocprofv3 --pmc
 # SQ_INSTS_VALU, and the FP64 FMA + MUL + ADD counters); valid only for the kernel sources
 # they were taken with.  The chip issues at most one wave64 FP64 VALU instruction per CU per
 # cycle: 256 CUs x 2.4 GHz.
-VALU_FP64 = {"sources_sha256_16": "c8486118afa3a515", "insts": 5.374e11,
-             "fp64_insts": 1.796e11 + 4.133e10 + 3.641e10}
+VALU_FP64 = {"sources_sha256_16": "c786dc84f9a7d3dc", "insts": 5.494e11,
+             "fp64_insts": 1.784e11 + 4.259e10 + 3.764e10}
 VALU_ISSUE_PER_S = 256 * 2.4e9
 
 
