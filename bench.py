@@ -49,25 +49,25 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU = 78.6e12      # MI355X FP64 vector FLOP/s
 PEAK_FP32_VALU = 157.3e12
 
-# HBM bytes of one FP64 k_rates launch on this workload from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes, each scaled by the counter's reading for a plain kernel that reads and
-# writes 256 MiB; valid only for the kernel sources they were taken with.
-TRAFFIC_FP64 = {"sources_sha256_16": "c786dc84f9a7d3dc", "bytes": 3.658e8 + 4.114e8}
-
-# Wavefront VALU instructions of one FP64 k_rates launch on this workload (rocprofv3 --pmc
-# SQ_INSTS_VALU, and the FP64 FMA + MUL + ADD counters); valid only for the kernel sources
-# they were taken with.  The chip issues at most one wave64 FP64 VALU instruction per CU per
-# cycle: 256 CUs x 2.4 GHz.
-VALU_FP64 = {"sources_sha256_16": "c786dc84f9a7d3dc", "insts": 5.494e11,
-             "fp64_insts": 1.784e11 + 4.259e10 + 3.764e10}
+# Counter readings of one FP64 k_rates launch on this workload, from the rocprofv3 summary
+# named in "source" (FETCH_SIZE and WRITE_SIZE scaled by their readings for a plain kernel
+# that reads and writes 256 MiB; SQ_INSTS_VALU and the FP64 FMA + MUL + ADD counters).  They
+# are reported only while kernel_build_key() equals "build_key": the kernel sources without
+# comments, the hipcc flags and the ROCm release they were taken with.  The chip issues at
+# most one wave64 FP64 VALU instruction per CU per cycle: 256 CUs x 2.4 GHz.
+COUNTERS_FP64 = {"build_key": None, "source": "profiles/k_rates_diamond8x8x8_fp64.md",
+                 "traffic_bytes": None, "valu_insts": None, "fp64_insts": None,
+                 "mfma_insts": None}
 VALU_ISSUE_PER_S = 256 * 2.4e9
 
 
-def kernel_sources_hash():
-    """sha256 (first 16 hex digits) of the rate kernel's sources with comments and blank
-    lines removed, so that a comment edit does not invalidate the counter readings."""
+def kernel_build_key():
+    """sha256 (first 16 hex digits) of what the rate kernel's machine code depends on: its
+    sources with comments and blank lines removed (a comment edit does not invalidate the
+    counter readings), the hipcc flags of the build, and the ROCm release."""
     import hashlib
     import re
+    from paper_2104_04895_amd import build as hb
     h = hashlib.sha256()
     for f in ("fp4_kernels.hip", "fp4_device.h", "fp4_internal.h"):
         with open(os.path.join(ROOT, "paper_2104_04895_amd", "csrc", f)) as fh:
@@ -75,6 +75,12 @@ def kernel_sources_hash():
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
         h.update("\n".join(ln for ln in lines if ln.strip()).encode())
+    h.update(" ".join(hb.HIPCC_FLAGS).encode())
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            h.update(fh.read().strip().encode())
+    except OSError:
+        h.update(b"unknown-rocm")
     return h.hexdigest()[:16]
 
 
@@ -463,11 +469,11 @@ def phase_space_main(args):
     ctx.close()
 
 
-def large_main(args):
+def large_leg(subset, with_sb01=True):
     """16x16x16 grid (24 576 modes), second-shell FC4, T = 300 K: a seeded random subset of
-    512 target modes in FP64 and with the FP32 contraction, every rate of the FP32 path
-    compared with the FP64 path, and in FP64 at scalebroad 0.1; full-grid times are
-    extrapolated from the subset."""
+    `subset` target modes in FP64 and with the FP32 contraction, every rate of the FP32 path
+    compared with the FP64 path, and (with_sb01) in FP64 at scalebroad 0.1; full-grid times
+    are extrapolated from the subset."""
     import synth
     import paper_2104_04895_amd as fp4
 
@@ -480,7 +486,7 @@ def large_main(args):
     ctx.set_param(fp4.FP4_PARAM_PROFILE, 1)
     rng = np.random.default_rng(1003)
     act = np.flatnonzero(inst.omega.reshape(-1) > 0)
-    targets = np.sort(rng.choice(act, size=args.subset, replace=False)).astype(np.int32)
+    targets = np.sort(rng.choice(act, size=subset, replace=False)).astype(np.int32)
     log(f"16^3 workload: {inst.nmodes} modes, {inst.fc4.n} quartets, subset {len(targets)}")
     out = {}
     r64 = None
@@ -499,16 +505,18 @@ def large_main(args):
             out[name]["max_rel_err_vs_fp64_path"] = float(rel.max())
             out[name]["median_rel_err_vs_fp64_path"] = float(np.median(rel[r64 > 0]))
         log(f"{name}: {wall:.1f} s, kernel {tm['ms_main']:.0f} ms, {int(cnt.sum())} processes")
-    # the paper's cost figure is quoted for a 16x16x16 grid at scalebroad 0.1: same subset
-    t0 = time.perf_counter()
-    _, _, cnt01 = ctx.compute_rates4(inst.T, 0.1, 7, fp4.FP4_FP64, targets)
-    tm = ctx.last_timing()
-    out["fp64_sb0.1"] = {"wall_s": time.perf_counter() - t0, "kernel_ms": tm["ms_main"],
-                         "processes": int(cnt01.sum()),
-                         "full_grid_seconds_extrapolated": tm["ms_main"] / 1e3 * len(act) / len(targets)}
-    log(f"fp64 sb 0.1: kernel {tm['ms_main']:.0f} ms, {int(cnt01.sum())} processes")
+    if with_sb01:
+        # the paper's cost figure is quoted for a 16x16x16 grid at scalebroad 0.1: same subset
+        t0 = time.perf_counter()
+        _, _, cnt01 = ctx.compute_rates4(inst.T, 0.1, 7, fp4.FP4_FP64, targets)
+        tm = ctx.last_timing()
+        out["fp64_sb0.1"] = {"wall_s": time.perf_counter() - t0, "kernel_ms": tm["ms_main"],
+                             "processes": int(cnt01.sum()),
+                             "full_grid_seconds_extrapolated": tm["ms_main"] / 1e3 * len(act) / len(targets)}
+        log(f"fp64 sb 0.1: kernel {tm['ms_main']:.0f} ms, {int(cnt01.sum())} processes")
     full = out["fp64"]["kernel_ms"] / 1e3 * len(act) / len(targets)
-    res = {
+    ctx.close()
+    return {
         "metric": "4ph processes/sec and rates time-to-solution; FP64 vs mixed at stated rel. err",
         "value": out["fp64"]["processes_per_s"], "unit": "processes/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
@@ -519,8 +527,60 @@ def large_main(args):
         "full_grid_fp64_seconds_extrapolated": full,
         "fp32_speedup": out["fp64"]["kernel_ms"] / out["fp32"]["kernel_ms"],
     }
-    print(json.dumps(res))
-    ctx.close()
+
+
+def large_main(args):
+    print(json.dumps(large_leg(args.subset)))
+
+
+def cpu_baseline_leg(inst, dq, gpu_proc_per_s):
+    """The oracle, as it stands, on the host cores: 8 target modes stratified by frequency
+    (evenly spaced ranks among the active modes) x 32 evenly spaced partner points q' of the
+    8x8x8 workload, both temperatures, all channels; scaled to processes/s."""
+    import oracle
+    m = oracle.Model.from_instance(inst)
+    om = inst.omega.reshape(-1)
+    act = np.flatnonzero(om > 0)
+    order = act[np.argsort(om[act], kind="stable")]
+    targets = order[np.linspace(0, len(order) - 1, 8).round().astype(int)].astype(np.int32)
+    q1 = np.arange(0, inst.nq, inst.nq // 32)
+    t1 = time.perf_counter()
+    _, c_o = oracle.rates4_partners(m, inst.T, inst.scalebroad, inst.mask, dq, targets, q1)
+    dt = time.perf_counter() - t1
+    nproc = int(c_o.sum())
+    return {"value": nproc / dt, "unit": "processes/s", "cores": oracle.max_threads(),
+            "kind": "oracle", "host_cpus": os.cpu_count(),
+            "sample": f"8 target modes stratified by frequency x {len(q1)} of {inst.nq} partner "
+                      f"q' points of the 8x8x8 workload, both temperatures, all channels "
+                      f"({nproc} processes, {dt:.1f} s)",
+            "gpu_over_cpu": gpu_proc_per_s / (nproc / dt)}
+
+
+def small_oracle_leg(fp4):
+    """The small 3x3x3 workload (162 modes, first-shell FC4, 300 K): the complete oracle on 1
+    thread and on all host threads against the library's synchronous call."""
+    import oracle
+    import synth
+    inst = synth.small()
+    dq = oracle.default_dq(inst.cr.A, inst.grid)
+    m = oracle.Model.from_instance(inst)
+    t0 = time.perf_counter()
+    r1, _, c1 = oracle.rates4(m, inst.T, 1.0, 7, dq, nthreads=1)
+    t_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.rates4(m, inst.T, 1.0, 7, dq)
+    t_all = time.perf_counter() - t0
+    with fp4.Context(0) as c:
+        c.load_instance(inst, dq=dq)
+        c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)       # warm
+        t0 = time.perf_counter()
+        r, _, cnt = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+        t_gpu = time.perf_counter() - t0
+    rel = np.abs(r - r1) / np.maximum(np.abs(r1), 1e-300)
+    return {"workload": "diamond-structure 3x3x3 (162 modes), first-shell FC4 (58 quartets), 300 K",
+            "processes": int(c1.sum()), "oracle_s_1_thread": t_one, "oracle_s_all_threads": t_all,
+            "oracle_threads": oracle.max_threads(), "gpu_sync_call_s": t_gpu,
+            "counts_equal": bool(np.array_equal(cnt, c1)), "max_rel_err_fp64": float(rel.max())}
 
 
 def main():
@@ -531,6 +591,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 side measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the 16x16x16 subset leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the steps, run one elementwise pass that reads and writes "
                          "256 MiB (calibrates hardware traffic counters)")
@@ -652,21 +713,24 @@ def main():
     t_main = float(np.mean(main_ms)) / 1e3
     peak = PEAK_FP64_VALU if prec == fp4.FP4_FP64 else PEAK_FP32_VALU
     achieved = flops / t_main
-    traffic = None
-    if prec == fp4.FP4_FP64 and kernel_sources_hash() == TRAFFIC_FP64["sources_sha256_16"]:
-        traffic = TRAFFIC_FP64["bytes"]
+    counters = (prec == fp4.FP4_FP64 and COUNTERS_FP64["build_key"] is not None
+                and kernel_build_key() == COUNTERS_FP64["build_key"])
+    traffic = COUNTERS_FP64["traffic_bytes"] if counters else None
 
     extras = {
         "candidates_per_s": candidates / (ms_per_step / 1e3),
         "candidates_per_step": candidates,
         "contracted_blocks_per_step": stats["blocks"],
         "hbm_gb_per_s": (traffic / t_main / 1e9) if traffic else None,
+        "counters_source": COUNTERS_FP64["source"] if counters else None,
+        "kernel_build_key": kernel_build_key(),
     }
-    if prec == fp4.FP4_FP64 and kernel_sources_hash() == VALU_FP64["sources_sha256_16"]:
-        extras["valu"] = {"insts_per_launch": VALU_FP64["insts"],
-                          "issue_frac": VALU_FP64["insts"] / (t_main * VALU_ISSUE_PER_S),
-                          "fp64_fma_mul_add_share": VALU_FP64["fp64_insts"] / VALU_FP64["insts"]}
-    extras["mfma_utilisation"] = 0.0   # the rate kernel has no dense contraction to put there
+    if counters:
+        extras["valu"] = {"insts_per_launch": COUNTERS_FP64["valu_insts"],
+                          "issue_frac": COUNTERS_FP64["valu_insts"] / (t_main * VALU_ISSUE_PER_S),
+                          "fp64_fma_mul_add_share": COUNTERS_FP64["fp64_insts"] / COUNTERS_FP64["valu_insts"]}
+        # matrix-core instructions issued by the rate kernel (SQ_INSTS_VALU_MFMA_* counters)
+        extras["mfma_insts_per_launch"] = COUNTERS_FP64["mfma_insts"]
     # time to solution: the synchronous call, rates and counts copied back to the host
     t0 = time.perf_counter()
     ctx.compute_rates4(inst.T, inst.scalebroad, inst.mask, prec)
@@ -682,20 +746,16 @@ def main():
                                       "max_rel_err_vs_fp64_path": float(rel.max()),
                                       "median_rel_err_vs_fp64_path": float(np.median(rel[rates64 > 0]))}
 
+    if not args.no_large:
+        # the 16x16x16 workload (the paper's BAs grid) on a 512-mode subset, FP64 and FP32
+        print("# 16x16x16 subset leg", file=sys.stderr, flush=True)
+        extras["large_16cubed_subset"] = large_leg(512, with_sb01=False)
+
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        m = oracle.Model.from_instance(inst)
-        q1 = np.arange(0, inst.nq, 16)
-        target = [100]
-        t1 = time.perf_counter()
-        _, c_o = oracle.rates4_partners(m, inst.T, inst.scalebroad, inst.mask, dq, target, q1)
-        dt = time.perf_counter() - t1
-        nproc = int(c_o.sum())
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": nproc / dt, "unit": "processes/s", "cores": cores, "kind": "oracle",
-               "sample": f"1 target mode x {len(q1)} of {inst.nq} partner q' points of the "
-                         f"8x8x8 workload, both temperatures ({nproc} processes, {dt:.1f} s)"}
+        print("# CPU baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_leg(inst, dq, processes / (ms_per_step / 1e3))
+        extras["small_3cubed_oracle"] = small_oracle_leg(fp4)
 
     out = {
         "metric": "4ph processes/sec and rates time-to-solution; FP64 vs mixed at stated rel. err",

@@ -119,7 +119,12 @@ int fp4_load_modes(fp4_ctx *ctx, int32_t nq, int32_t nb, const double *omega,
  *                     the home cell), each component in [-64, 64]
  *   phi   [n][81]     eV/Angstrom^4, index ((alpha*3 + beta)*3 + gamma)*3 + theta
  * 1 <= n <= 2^20.  The list need not be symmetric; the rate is evaluated for whatever is
- * given. */
+ * given.  When the list is symmetric under the exchange of slots 3 and 4 (for every entry
+ * (i,j,k,l; Rj,Rk,Rl) the entry (i,j,l,k; Rj,Rl,Rk) holds Phi with gamma and theta
+ * exchanged, entries with equal atoms and cells summed, to 1e-12 of max |Phi|; permutation
+ * symmetry of Eq. TS implies it) the redistribution matrix element is symmetric in
+ * lambda'' and lambda''' and one contraction serves both members of each mirror pair;
+ * otherwise every redistribution block is contracted on its own (about 1.5x the work). */
 int fp4_load_fc4(fp4_ctx *ctx, int32_t nquart, const int32_t *atoms, const int32_t *cells,
                  const double *phi);
 
@@ -146,6 +151,22 @@ int fp4_compute_rates4_subset(fp4_ctx *ctx, const double *T, int32_t nT, double 
                               uint32_t mask, int32_t precision, const int32_t *targets,
                               int32_t ntargets, double *rates, double *rates_by_channel,
                               int64_t *counts);
+
+/* Normal and Umklapp parts of the rates in one pass (the two process classes named after
+ * Eq. tao0, Q = 0 and Q != 0, with Q and the first-zone images as for FP4_PARAM_QCLASS; the
+ * paper's outputs BTE.w_4ph_normal and BTE.w_4ph_Umklapp beside BTE.w_4ph, App. A).  Every
+ * kept process is classed once per block and summed into its class; the total is their sum.
+ *   targets          host [ntargets] mode ids, or NULL for every mode (ntargets ignored)
+ *   rates            host [nT][nt] total (nullable), nt = ntargets or nq*nb
+ *   rates_normal     host [nT][nt] normal processes (nullable)
+ *   rates_umklapp    host [nT][nt] Umklapp processes (nullable; not both class outputs NULL)
+ *   counts           host [nt][3] kept processes per channel, both classes, or NULL
+ * Other arguments as for fp4_compute_rates4.  FP4_PARAM_QCLASS is ignored by this call; with
+ * FP4_PARAM_PHASE_SPACE set it returns FP4_E_UNSUPPORTED.  Synchronous. */
+int fp4_compute_rates4_classes(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                               uint32_t mask, int32_t precision, const int32_t *targets,
+                               int32_t ntargets, double *rates, double *rates_normal,
+                               double *rates_umklapp, int64_t *counts);
 
 /* Same on the irreducible part of the grid under a point group supplied by the caller.
  *   rot [nrot][9] integer matrices (row-major) acting on reduced q coordinates,
@@ -241,6 +262,25 @@ int fp4_compute_rates3(fp4_ctx *ctx, const double *T, int32_t nT, double scalebr
 int fp4_surrogate_features(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
                            const int32_t *targets, int32_t ntargets, const float *shift,
                            const float *scale, float *X, double *rates3);
+
+/* RTA lattice thermal conductivity with three- and four-phonon scattering:
+ *   kappa^{ab}(T) = 1/(N Omega) sum_lambda C_lambda v^a v^b tau_lambda,
+ *   C_lambda = k_B x^2 n0 (n0 + 1), x = hbar w / (k_B T),  1/tau = 1/tau3 + 1/tau4,
+ * i.e. Eq. tao0 without the isotope term and F = tau v (Eq. BTE in the relaxation-time
+ * approximation); Omega = |det A|.  The paper takes the conductivity from ShengBTE without
+ * printing it; this is the standard kinetic form.  The rates are the library's own: the
+ * four-phonon rate of every mode (all channels, `precision` of the contraction) and the
+ * three-phonon rate (FP64), both at `scalebroad`.  Modes with w <= 0 or with a zero total
+ * rate take no part.
+ *   T[nT]      1 <= nT <= 8 temperatures (K)
+ *   kappa      host [nT][3][3] W/(m K) (required)
+ *   nskip      host [nT] active modes left out for a zero total rate, or NULL
+ *   rates3, rates4   host [nT][nq*nb] the rates used (1/ps), or NULL
+ * Requires fp4_load_lattice, fp4_load_modes, fp4_load_fc4 and fp4_load_fc3; with
+ * FP4_PARAM_PHASE_SPACE or FP4_PARAM_QCLASS set it returns FP4_E_UNSUPPORTED.  Synchronous. */
+int fp4_compute_kappa_rta(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                          int32_t precision, double *kappa, int64_t *nskip, double *rates3,
+                          double *rates4);
 
 /* ---------------------------------------------------------------- batched instances
  * Several crystals (uneven branch counts, grids, quartet lists) evaluated by one captured HIP

@@ -56,6 +56,12 @@ def lib():
         L.oracle_v3.restype = ctypes.c_int
         L.oracle_c3.restype = f64
         L.oracle_c3.argtypes = []
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_kappa_rta.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P]
+        L.oracle_kappa_rta.restype = ctypes.c_int
+        L.oracle_first_zone.argtypes = [P, P, i32, P, P]
+        L.oracle_first_zone.restype = ctypes.c_int
         L.oracle_v4.argtypes = [P, i32, P, P, P, P, i32, P, P, P, i32, P, P, P]
         L.oracle_v4.restype = ctypes.c_int
         for name in ("oracle_hbar_over_kb", "oracle_c4"):
@@ -194,6 +200,19 @@ def rates4_partners(model: Model, T, scalebroad, mask, dq, targets, q1list, wind
     return rates, counts
 
 
+def first_zone(A, grid, iq) -> np.ndarray:
+    """First-zone images k[n][3] (Cartesian, 1/Angstrom) of the grid points iq, as the
+    normal / Umklapp split uses them (A: lattice vectors as rows)."""
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+    g = np.ascontiguousarray(grid, dtype=np.int32)
+    iq = np.ascontiguousarray(np.atleast_1d(iq), dtype=np.int32)
+    k = np.zeros((len(iq), 3))
+    rc = lib().oracle_first_zone(_p(A), _p(g), len(iq), _p(iq), _p(k))
+    if rc != 0:
+        raise ValueError(f"oracle_first_zone returned {rc}")
+    return k
+
+
 def v4(model: Model, modes4, signs4) -> np.ndarray:
     """V (Eq. V4) for explicit processes: modes4[n][4] mode ids, signs4[n][4] slot signs."""
     modes4 = np.ascontiguousarray(modes4, dtype=np.int32).reshape(-1, 4)
@@ -241,6 +260,11 @@ def v3(model: Model, fc3, modes3, signs3) -> np.ndarray:
     return V
 
 
+def max_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use by default."""
+    return int(lib().oracle_max_threads())
+
+
 def c3() -> float:
     return float(lib().oracle_c3())
 
@@ -259,3 +283,24 @@ def bose(omega, T) -> float:
 
 def delta(dw, sigma2, sigma_min=1e-4) -> float:
     return float(lib().oracle_delta(float(dw), float(sigma2), float(sigma_min)))
+
+
+def kappa_rta(grid, natoms, omega, vel, A, T, rates3, rates4):
+    """RTA thermal conductivity kappa[nT][3][3] (W/(m K)) from three- and four-phonon rates
+    [nT][nmodes] (1/ps), and the number of active modes skipped for a zero total rate."""
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    g = np.ascontiguousarray(grid, dtype=np.int32)
+    om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1)
+    v = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+    r3 = np.ascontiguousarray(rates3, dtype=np.float64).reshape(len(T), -1)
+    r4 = np.ascontiguousarray(rates4, dtype=np.float64).reshape(len(T), -1)
+    if r3.shape[1] != om.size or r4.shape[1] != om.size:
+        raise ValueError("rates must be [nT][nmodes]")
+    kappa = np.zeros((len(T), 3, 3))
+    nskip = np.zeros(len(T), dtype=np.int64)
+    rc = lib().oracle_kappa_rta(_p(g), int(natoms), _p(om), _p(v), _p(A), _p(T), len(T), _p(r3),
+                                _p(r4), _p(kappa), _p(nskip))
+    if rc != 0:
+        raise ValueError(f"oracle_kappa_rta returned {rc}")
+    return kappa, nskip

@@ -57,6 +57,15 @@ static const double ANG = 1.0e-10;            /* m     */
 /* hbar/k_B in K*ps */
 double oracle_hbar_over_kb(void) { return HBAR / KB * 1.0e12; }
 
+/* Threads a parallel region of the oracle uses when nthreads is 0 (reported with timings). */
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Prefactor of Eq. 4phgamma without the 1/N factors:
  *   G[1/ps] = C4 * occ * |V|^2 * delta[ps] / (w w' w'' w''')[(rad/ps)^4]
  * for V in eV / (A^4 amu^2):  C4 = hbar^2 pi / 8 * (eV/(A^4 amu^2))^2 * 1e-72. */
@@ -187,6 +196,22 @@ static void first_zone(const model_t *m, const double B[9], int iq, double k[3])
                     k[0] = c[0]; k[1] = c[1]; k[2] = c[2];
                 }
             }
+}
+
+/* Public: the first-zone images of a list of grid points, k_out[n][3] Cartesian (1/Angstrom,
+ * 2 pi included), as used by the normal / Umklapp split.  A[9]: lattice vectors as rows. */
+int oracle_first_zone(const double A[9], const int32_t grid[3], int32_t n, const int32_t *iq,
+                      double *k_out) {
+    model_t m;
+    m.g[0] = grid[0]; m.g[1] = grid[1]; m.g[2] = grid[2];
+    m.N = grid[0] * grid[1] * grid[2];
+    double B[9];
+    recip(A, B);
+    for (int i = 0; i < n; ++i) {
+        if (iq[i] < 0 || iq[i] >= m.N) return -1;
+        first_zone(&m, B, iq[i], k_out + 3 * i);
+    }
+    return 0;
 }
 
 /* exp(i q.R) for grid point iq and integer cell R (lattice coordinates). */
@@ -709,5 +734,49 @@ int oracle_rates3(const int32_t grid[3], int32_t natoms, const double *mass,
     }
     free(occ);
     model_free(&m);
+    return 0;
+}
+
+/* ======================================================================= thermal conductivity
+ * Public: RTA lattice thermal conductivity with three- and four-phonon scattering (the
+ * single-mode relaxation time of Eq. tao0 without the isotope term, F = tau v from Eq. BTE
+ * in the relaxation-time approximation).  The paper takes the conductivity expression from
+ * ShengBTE without printing it; the reading used here is the standard kinetic one:
+ *   kappa^{ab} = 1/(N Omega) sum_lambda C_lambda v_lambda^a v_lambda^b tau_lambda,
+ *   C_lambda = k_B x^2 n0 (n0 + 1),  x = hbar w / (k_B T),
+ *   1/tau_lambda = 1/tau3 + 1/tau4,
+ * with Omega the cell volume |det A|.  Modes with w <= 0 or with zero total rate take no part
+ * (their count is returned in nskip[t]).  Inputs rates3/rates4 [nT][nmodes] in 1/ps, omega
+ * rad/ps, vel [nmodes][3] A/ps, A [9] Angstrom; output kappa [nT][3][3] in W/(m K). */
+int oracle_kappa_rta(const int32_t grid[3], int32_t natoms, const double *omega,
+                     const double *vel, const double A[9], const double *T, int32_t nT,
+                     const double *rates3, const double *rates4, double *kappa,
+                     int64_t *nskip) {
+    if (natoms <= 0 || nT <= 0) return -1;
+    const long N = (long)grid[0] * grid[1] * grid[2];
+    const long nmodes = N * 3 * natoms;
+    const double omega_cell = fabs(A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                                   A[2] * (A[3] * A[7] - A[4] * A[6])) * 1e-30;   /* m^3 */
+    const double hk = oracle_hbar_over_kb();
+    for (int t = 0; t < nT; ++t) {
+        double s[9], c[9];
+        for (int e = 0; e < 9; ++e) { s[e] = 0.0; c[e] = 0.0; }
+        int64_t skipped = 0;
+        for (long mu = 0; mu < nmodes; ++mu) {
+            const double w = omega[mu];
+            const double rate = rates3[(size_t)t * nmodes + mu] + rates4[(size_t)t * nmodes + mu];
+            if (!(w > 0.0) || !(rate > 0.0)) { skipped += w > 0.0; continue; }
+            const double x = hk * w / T[t];
+            const double n0 = oracle_bose(w, T[t]);
+            const double cap = KB * x * x * n0 * (n0 + 1.0);          /* J/K */
+            const double tau = 1e-12 / rate;                            /* s */
+            const double *v = vel + 3 * (size_t)mu;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    neumaier(&s[3 * a + b], &c[3 * a + b], cap * (v[a] * 100.0) * (v[b] * 100.0) * tau);
+        }
+        for (int e = 0; e < 9; ++e) kappa[(size_t)t * 9 + e] = (s[e] + c[e]) / ((double)N * omega_cell);
+        if (nskip) nskip[t] = skipped;
+    }
     return 0;
 }

@@ -44,6 +44,7 @@ EXPORTED = [
     "fp4_mlp_last_error", "fp4_mlp_num_params", "fp4_mlp_get_params", "fp4_mlp_set_params",
     "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict", "fp4_load_fc3",
     "fp4_compute_rates3", "fp4_surrogate_features", "fp4_compute_rates4_wedge",
+    "fp4_compute_rates4_classes", "fp4_compute_kappa_rta",
 ]
 FP4_NFEAT = 18
 
@@ -85,6 +86,8 @@ def lib():
         L.fp4_compute_rates4.argtypes = [P, P, i32, f64, u32, i32, P, P, P]
         L.fp4_compute_rates4_subset.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P]
         L.fp4_compute_rates4_wedge.argtypes = [P, P, i32, f64, u32, i32, i32, P, P, P, P]
+        L.fp4_compute_rates4_classes.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P, P]
+        L.fp4_compute_kappa_rta.argtypes = [P, P, i32, f64, i32, P, P, P, P]
         L.fp4_compute_rates4_async.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
         L.fp4_debug_matrix_elements.argtypes = [P, i32, P, i32, P]
         L.fp4_last_stats.argtypes = [P, P, P, P]
@@ -254,6 +257,38 @@ class Context:
                                                    _p(rates), _p(rch), _p(cnt))
         self._check(rc, "fp4_compute_rates4")
         return rates, rch, cnt
+
+    def compute_kappa_rta(self, T, scalebroad=1.0, precision=FP4_FP64):
+        """RTA conductivity with 3ph + 4ph rates.  Returns (kappa[nT][3][3] W/(m K),
+        nskip[nT], rates3[nT][nmodes], rates4[nT][nmodes])."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        nm = self.nq * self.nb
+        kappa = np.zeros((len(T), 3, 3))
+        nskip = np.zeros(len(T), dtype=np.int64)
+        r3 = np.zeros((len(T), nm))
+        r4 = np.zeros((len(T), nm))
+        self._check(self._L.fp4_compute_kappa_rta(self._h, _p(T), len(T), float(scalebroad),
+                                                  int(precision), _p(kappa), _p(nskip), _p(r3),
+                                                  _p(r4)), "fp4_compute_kappa_rta")
+        return kappa, nskip, r3, r4
+
+    def compute_rates4_classes(self, T, scalebroad=1.0, mask=7, precision=FP4_FP64,
+                               targets=None, counts=True):
+        """Total, normal and Umklapp rates from one pass.  Returns (rates, normal, umklapp,
+        counts), the rate arrays [nT][nt]."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        if targets is None:
+            nt = self.nq * self.nb
+        else:
+            targets = np.ascontiguousarray(targets, dtype=np.int32)
+            nt = len(targets)
+        r, rn, ru = (np.zeros((len(T), nt)) for _ in range(3))
+        cnt = np.zeros((nt, 3), dtype=np.int64) if counts else None
+        self._check(self._L.fp4_compute_rates4_classes(self._h, _p(T), len(T), float(scalebroad),
+                                                       int(mask), int(precision), _p(targets), nt,
+                                                       _p(r), _p(rn), _p(ru), _p(cnt)),
+                    "fp4_compute_rates4_classes")
+        return r, rn, ru, cnt
 
     def compute_rates4_wedge(self, T, scalebroad, mask, precision, rotations, counts=True):
         """Rates on the irreducible grid points under integer rotations (reduced q

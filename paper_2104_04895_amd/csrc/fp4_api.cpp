@@ -92,12 +92,14 @@ struct fp4_ctx {
   DevBuf d_qord, d_qordw, d_qimg;
   std::vector<int> h_qimg;
   int qclass = 0, harmonic = 0;
+  // the quartet list is symmetric under the exchange of slots 3 and 4 (see fp4_load_fc4)
+  bool sym34 = false;
   double w_lo = 0.0, w_hi = 0.0, v_hi = 0.0;
   DevBuf d_g_d, d_kl, d_cs, d_cj, d_ca, d_cq, d_qi, d_qb, d_qphi, d_avec, d_bvec, d_dvec;
   DevBuf d_T, d_occ, d_iocc, d_targets, d_U, d_partial, d_pcount, d_blocks;
   DevBuf d_rates, d_rch, d_counts, d_quads, d_tslot, d_V;
   DevBuf d3_jk, d3_ti, d3_td, d3_trk, d3_phi, d3_rkv, d3_dv, d3_PH3, d3_U, d3_targets, d3_rates, d3_counts;
-  DevBuf df_g4, df_X, df_shift;
+  DevBuf df_g4, df_X, df_shift, d_kappa;
 
   // statistics / timing of the last call
   long long st_processes = 0, st_candidates = 0, st_blocks = 0;
@@ -254,41 +256,43 @@ int ensure_tables(fp4_ctx *ctx) {
     ctx->w_lo = wlo;
     ctx->w_hi = whi;
     ctx->v_hi = vhi;
-    // first-zone image of every grid point (normal / Umklapp classes): the shift m in
-    // {-2..1}^3 of smallest |sum_d (n_d/N_d + m_d) b_d|, ties (relative 1e-10) to the first m
-    // in the order m1, m2, m3
+    // First-zone image of every grid point (normal / Umklapp classes): among the 64 shifts
+    // m in {-2..1}^3 the reduced vector f = n/N + m of smallest |f|_G^2 = f^T G f, with
+    // G = B B^T the reciprocal metric (B rows = b_d, 2 pi included; G = 4 pi^2 (A A^T)^-1).
+    // Images whose squared lengths lie within a relative 1e-10 of the shortest are equal
+    // lengths (points on the zone boundary); of those the first in the order m1, m2, m3
+    // (m1 slowest) is taken.  Stored as integer numerators n_d + m_d N_d.
     {
-      double Bv[9];
-      const double *a0 = ctx->A, *a1 = ctx->A + 3, *a2 = ctx->A + 6;
-      const double det = a0[0] * (a1[1] * a2[2] - a1[2] * a2[1]) - a0[1] * (a1[0] * a2[2] - a1[2] * a2[0]) +
-                         a0[2] * (a1[0] * a2[1] - a1[1] * a2[0]);
-      const double *pr[3][2] = {{a1, a2}, {a2, a0}, {a0, a1}};
-      for (int i = 0; i < 3; ++i) {
-        const double *u = pr[i][0], *v = pr[i][1];
-        Bv[3 * i + 0] = 2.0 * M_PI * (u[1] * v[2] - u[2] * v[1]) / det;
-        Bv[3 * i + 1] = 2.0 * M_PI * (u[2] * v[0] - u[0] * v[2]) / det;
-        Bv[3 * i + 2] = 2.0 * M_PI * (u[0] * v[1] - u[1] * v[0]) / det;
-      }
+      const double *A = ctx->A;
+      double M[9];   // A A^T
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = A[3 * i] * A[3 * j] + A[3 * i + 1] * A[3 * j + 1] + A[3 * i + 2] * A[3 * j + 2];
+      const double dm = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+                        M[2] * (M[3] * M[7] - M[4] * M[6]);
+      const double c4pi2 = 4.0 * kPi * kPi / dm;
+      const double G[9] = {c4pi2 * (M[4] * M[8] - M[5] * M[7]), c4pi2 * (M[2] * M[7] - M[1] * M[8]),
+                           c4pi2 * (M[1] * M[5] - M[2] * M[4]), c4pi2 * (M[5] * M[6] - M[3] * M[8]),
+                           c4pi2 * (M[0] * M[8] - M[2] * M[6]), c4pi2 * (M[2] * M[3] - M[0] * M[5]),
+                           c4pi2 * (M[3] * M[7] - M[4] * M[6]), c4pi2 * (M[1] * M[6] - M[0] * M[7]),
+                           c4pi2 * (M[0] * M[4] - M[1] * M[3])};
       const int *g = ctx->grid;
       ctx->h_qimg.assign(4 * N, 0);
+      double len[64];
       for (size_t iq = 0; iq < N; ++iq) {
         const int n[3] = {(int)(iq % g[0]), (int)((iq / g[0]) % g[1]), (int)(iq / ((size_t)g[0] * g[1]))};
-        double best = -1.0;
-        int bm[3] = {0, 0, 0};
-        for (int m1 = -2; m1 <= 1; ++m1)
-          for (int m2 = -2; m2 <= 1; ++m2)
-            for (int m3 = -2; m3 <= 1; ++m3) {
-              const double f[3] = {(double)n[0] / g[0] + m1, (double)n[1] / g[1] + m2, (double)n[2] / g[2] + m3};
-              double l2 = 0.0;
-              for (int x = 0; x < 3; ++x) {
-                const double cx = f[0] * Bv[x] + f[1] * Bv[3 + x] + f[2] * Bv[6 + x];
-                l2 += cx * cx;
-              }
-              if (best < 0.0 || l2 < best * (1.0 - 1e-10)) {
-                best = l2;
-                bm[0] = m1; bm[1] = m2; bm[2] = m3;
-              }
-            }
+        double lmin = 1e300;
+        for (int s = 0; s < 64; ++s) {
+          const double f[3] = {(double)n[0] / g[0] + (s >> 4) - 2, (double)n[1] / g[1] + ((s >> 2) & 3) - 2,
+                               (double)n[2] / g[2] + (s & 3) - 2};
+          double l2 = 0.0;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) l2 += f[i] * G[3 * i + j] * f[j];
+          len[s] = l2;
+          lmin = std::min(lmin, l2);
+        }
+        int best = 0;
+        while (!(len[best] <= lmin * (1.0 + 1e-10))) ++best;
+        const int bm[3] = {(best >> 4) - 2, ((best >> 2) & 3) - 2, (best & 3) - 2};
         for (int d = 0; d < 3; ++d) ctx->h_qimg[4 * iq + d] = n[d] + bm[d] * g[d];
       }
       if ((rc = upload(ctx, ctx->d_qimg, ctx->h_qimg.data(), ctx->h_qimg.size()))) return rc;
@@ -366,6 +370,7 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
   a.c_min = ctx->sigma_min * ctx->sigma_min;
   a.kpref = (ctx->harmonic ? 1.0 : c4_prefactor()) / ((double)ctx->N * (double)ctx->N);
   a.harmonic = ctx->harmonic;
+  a.mirror = ctx->sym34 ? 1 : 0;
   a.nT = nT;
   a.mask = mask;
   a.qclass = ctx->qclass;
@@ -554,7 +559,8 @@ void fp4_destroy(fp4_ctx *ctx) {
                    &ctx->d_rch, &ctx->d_counts, &ctx->d_quads, &ctx->d_tslot, &ctx->d_V,
                    &ctx->d3_jk, &ctx->d3_ti, &ctx->d3_td, &ctx->d3_trk, &ctx->d3_phi,
                    &ctx->d3_rkv, &ctx->d3_dv, &ctx->d3_PH3, &ctx->d3_U, &ctx->d3_targets,
-                   &ctx->d3_rates, &ctx->d3_counts, &ctx->df_g4, &ctx->df_X, &ctx->df_shift};
+                   &ctx->d3_rates, &ctx->d3_counts, &ctx->df_g4, &ctx->df_X, &ctx->df_shift,
+                   &ctx->d_kappa};
   for (DevBuf *b : all) release(*b);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -631,6 +637,9 @@ int fp4_load_modes(fp4_ctx *ctx, int32_t nq, int32_t nb, const double *omega,
     FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->have_modes = true;
     ctx->tables_dirty = true;
+    // the per-q tables are built as soon as modes and quartets are both loaded, so that no
+    // compute call has to allocate them
+    if (ctx->have_fc4 && (rc = ensure_tables(ctx))) return rc;
     ctx->err.clear();
     return FP4_OK;
   } catch (const std::bad_alloc &) {
@@ -672,6 +681,50 @@ int fp4_load_fc4(fp4_ctx *ctx, int32_t nquart, const int32_t *atoms, const int32
         return id;
       };
       qs[n] = Q{at[0], at[1], at[2], at[3], intern(amap, a), intern(bmap, b), intern(dmap, d), n};
+    }
+    // Symmetry under the exchange of slots 3 and 4: quartet (i, j, k, l; Rj, Rk, Rl) with
+    // Phi[a][b][g][t] and quartet (i, j, l, k; Rj, Rl, Rk) with Phi[a][b][t][g] contribute
+    // alike to Eq. V4, so for such a list the redistribution matrix element is symmetric in
+    // lambda'' and lambda''' and the kernel contracts one block of each mirror pair.  Entries
+    // with equal atoms and cells are summed first; a missing partner counts as zero.  The
+    // tolerance is 1e-12 of the largest |Phi|.
+    {
+      using Key = std::array<int, 13>;
+      std::map<Key, std::array<double, 81>> acc;
+      double pmax = 0.0;
+      for (int n = 0; n < nquart; ++n) {
+        Key key;
+        for (int x = 0; x < 4; ++x) key[x] = atoms[4 * n + x];
+        for (int x = 0; x < 9; ++x) key[4 + x] = cells[9 * n + x];
+        auto it = acc.find(key);
+        if (it == acc.end()) {
+          std::array<double, 81> z{};
+          it = acc.emplace(key, z).first;
+        }
+        for (int e = 0; e < 81; ++e) {
+          it->second[e] += phi[(size_t)81 * n + e];
+          pmax = std::max(pmax, std::fabs(phi[(size_t)81 * n + e]));
+        }
+      }
+      const double tol = 1e-12 * pmax;
+      bool sym = true;
+      const std::array<double, 81> zero{};
+      for (auto it = acc.begin(); sym && it != acc.end(); ++it) {
+        const Key &k0 = it->first;
+        Key k1 = k0;
+        std::swap(k1[2], k1[3]);
+        for (int x = 0; x < 3; ++x) std::swap(k1[7 + x], k1[10 + x]);
+        auto jt = acc.find(k1);
+        const std::array<double, 81> &p1 = jt == acc.end() ? zero : jt->second;
+        for (int ab = 0; ab < 9 && sym; ++ab)
+          for (int g = 0; g < 3 && sym; ++g)
+            for (int t = 0; t < 3; ++t)
+              if (std::fabs(it->second[ab * 9 + g * 3 + t] - p1[ab * 9 + t * 3 + g]) > tol) {
+                sym = false;
+                break;
+              }
+      }
+      ctx->sym34 = sym;
     }
     // groups (k, l, d) and combos (group, j, a), ordered
     std::sort(qs.begin(), qs.end(), [](const Q &x, const Q &y) {
@@ -744,6 +797,7 @@ int fp4_load_fc4(fp4_ctx *ctx, int32_t nquart, const int32_t *atoms, const int32
     FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->have_fc4 = true;
     ctx->tables_dirty = true;
+    if (ctx->have_modes && (rc = ensure_tables(ctx))) return rc;
     ctx->err.clear();
     return FP4_OK;
   } catch (const std::bad_alloc &) {
@@ -808,6 +862,36 @@ int fp4_compute_rates4_subset(fp4_ctx *ctx, const double *T, int32_t nT, double 
     (void)hipSetDevice(ctx->device);
     return compute_common(ctx, T, nT, scalebroad, mask, precision, targets, ntargets, rates,
                           rates_by_channel, counts);
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_compute_rates4_classes(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                               uint32_t mask, int32_t precision, const int32_t *targets,
+                               int32_t ntargets, double *rates, double *rates_normal,
+                               double *rates_umklapp, int64_t *counts) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    if (ctx->harmonic) return ctx->fail(FP4_E_UNSUPPORTED, "the class split takes rates, not phase spaces (FP4_PARAM_PHASE_SPACE must be 0)");
+    if (!rates_normal && !rates_umklapp) return ctx->fail(FP4_E_INVAL, "rates_normal or rates_umklapp is required");
+    (void)hipSetDevice(ctx->device);
+    const int nt = targets ? ntargets : ctx->N * ctx->nb;
+    if (nt < 1) return ctx->fail(FP4_E_INVAL, "need 1 <= ntargets <= nq*nb");
+    std::vector<double> tot((size_t)std::max(1, (int)nT) * nt), cls((size_t)std::max(1, (int)nT) * 3 * nt);
+    const int keep = ctx->qclass;
+    ctx->qclass = 3;
+    const int rc = compute_common(ctx, T, nT, scalebroad, mask, precision, targets, nt,
+                                  tot.data(), cls.data(), counts);
+    ctx->qclass = keep;
+    if (rc) return rc;
+    for (int t = 0; t < nT; ++t)
+      for (int i = 0; i < nt; ++i) {
+        if (rates) rates[(size_t)t * nt + i] = tot[(size_t)t * nt + i];
+        if (rates_normal) rates_normal[(size_t)t * nt + i] = cls[((size_t)t * 3 + 0) * nt + i];
+        if (rates_umklapp) rates_umklapp[(size_t)t * nt + i] = cls[((size_t)t * 3 + 1) * nt + i];
+      }
+    return FP4_OK;
   } catch (const std::bad_alloc &) {
     return ctx->fail(FP4_E_NOMEM, "host allocation failed");
   }
@@ -1250,6 +1334,56 @@ int fp4_surrogate_features(fp4_ctx *ctx, const double *T, int32_t nT, double sca
   }
 }
 
+int fp4_compute_kappa_rta(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                          int32_t precision, double *kappa, int64_t *nskip, double *rates3,
+                          double *rates4) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    std::vector<int> tl;
+    int rc = rates3_args(ctx, T, nT, scalebroad, nullptr, 0, tl);
+    if (rc) return rc;
+    if ((rc = check_compute_args(ctx, T, nT, scalebroad, 7u, precision))) return rc;
+    if (ctx->harmonic || ctx->qclass)
+      return ctx->fail(FP4_E_UNSUPPORTED, "the conductivity needs the full rates (FP4_PARAM_PHASE_SPACE and FP4_PARAM_QCLASS must be 0)");
+    if (!kappa) return ctx->fail(FP4_E_INVAL, "kappa output is required");
+    (void)hipSetDevice(ctx->device);
+    const int nt = (int)tl.size();
+    // four-phonon rates of every mode (all channels) into d_rates, three-phonon into d3_rates
+    if ((rc = upload(ctx, ctx->d_targets, tl.data(), tl.size()))) return rc;
+    if ((rc = ensure(ctx, ctx->d_rates, (size_t)nT * nt * sizeof(double)))) return rc;
+    if ((rc = ensure(ctx, ctx->d_counts, (size_t)nt * 3 * sizeof(long long)))) return rc;
+    if ((rc = enqueue(ctx, T, nT, scalebroad, 7u, precision, nt, ctx->stream, (double *)ctx->d_rates.p,
+                      nullptr, (long long *)ctx->d_counts.p, nullptr, nullptr)))
+      return rc;
+    if ((rc = enqueue_rates3(ctx, T, nT, scalebroad, tl))) return rc;
+    if ((rc = ensure(ctx, ctx->d_kappa, (size_t)nT * 10 * sizeof(double)))) return rc;
+    double *d_k = (double *)ctx->d_kappa.p;
+    long long *d_skip = (long long *)(d_k + (size_t)nT * 9);
+    const double *a = ctx->A;
+    const double vol = std::fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                                 a[2] * (a[3] * a[7] - a[4] * a[6])) * 1e-30;   // m^3
+    const double scale = 1.0 / ((double)ctx->N * vol);
+    fp4::Crystal c = make_crystal(ctx);
+    FP4_HIP(ctx, fp4::launch_kappa(c, (const double *)ctx->d_T.p, nT, hbar_over_kb_kps(),
+                                   (const double *)ctx->d_occ.p, (const double *)ctx->d3_rates.p,
+                                   (const double *)ctx->d_rates.p, scale, kKB, d_k, d_skip, ctx->stream));
+    FP4_HIP(ctx, hipMemcpyAsync(kappa, d_k, (size_t)nT * 9 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<long long> sk(nT);
+    FP4_HIP(ctx, hipMemcpyAsync(sk.data(), d_skip, (size_t)nT * sizeof(long long), hipMemcpyDeviceToHost, ctx->stream));
+    if (rates3)
+      FP4_HIP(ctx, hipMemcpyAsync(rates3, ctx->d3_rates.p, (size_t)nT * nt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (rates4)
+      FP4_HIP(ctx, hipMemcpyAsync(rates4, ctx->d_rates.p, (size_t)nT * nt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    FP4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (nskip)
+      for (int t = 0; t < nT; ++t) nskip[t] = sk[t];
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
 int fp4_last_stats(const fp4_ctx *ctx, int64_t *processes, int64_t *candidates, int64_t *blocks) {
   if (!ctx) return FP4_E_INVAL;
   if (processes) *processes = ctx->st_processes;
@@ -1323,6 +1457,7 @@ int prepare_instance(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t 
   a.c_min = ctx->sigma_min * ctx->sigma_min;
   a.kpref = (ctx->harmonic ? 1.0 : c4_prefactor()) / ((double)ctx->N * (double)ctx->N);
   a.harmonic = ctx->harmonic;
+  a.mirror = ctx->sym34 ? 1 : 0;
   a.nT = nT;
   a.mask = mask;
   a.qclass = ctx->qclass;

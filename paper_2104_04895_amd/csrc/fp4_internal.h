@@ -56,11 +56,18 @@ struct RateArgs {
   double kpref;             // C4 / N^2
   int nT;
   uint32_t mask;            // channel bits
-  int qclass;               // 0 all processes, 1 normal only (Q = 0), 2 Umklapp only
+  int qclass;               // 0 all processes, 1 normal only (Q = 0), 2 Umklapp only,
+                            // 3 both classes apart: partial slot 0 normal, 1 Umklapp
+                            // (all channels), 2 unused
   int harmonic;             // 0 rates; phase spaces with |V|^2 := 1: 1 WP4, 2 P4
+  int mirror;               // 1: the quartet list is symmetric under the slot-3/slot-4
+                            // exchange, so the redistribution blocks of q'' and q''' are
+                            // transposes and one contraction serves both; 0: every block
+                            // is contracted on its own
   const double *occ;        // [nT][N*nb]  n0 (0 for inactive modes)
   const double *inv_occ;    // [nT][N*nb]  1/n0 = expm1(hbar w / kT)
-  const int *targets;       // [nt] mode ids
+  const int *targets;       // [nt] mode ids, or null: target t is mode tbase + t
+  int tbase;                // first mode id when targets is null
   int nt;                   // targets in this batch
   int t0;                   // index of the first target of the batch in the output
   int qchunk;               // q' points per work-group
@@ -119,7 +126,12 @@ hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, doub
 hipError_t launch_occupations(const Crystal &c, const double *T, int nT, double hbar_over_kb,
                               double *occ, double *inv_occ, hipStream_t s);
 hipError_t launch_precontract(const Crystal &c, const int *targets, int nt, int fp32,
-                              void *U, hipStream_t s);
+                              void *U, hipStream_t s, int tbase = 0);
+// ordered reduction writing rates [nT][stride] (and per channel [nT][3][stride]) at columns
+// off .. off + nt - 1, counts [stride][3] at rows off ..
+hipError_t launch_reduce_strided(const RateArgs &a, int nt, int stride, int off, double *rates,
+                                 double *rates_ch, long long *counts, hipStream_t s);
+size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT);
 hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream_t s);
 hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double *rates_ch,
                          long long *counts, hipStream_t s);
@@ -138,6 +150,11 @@ hipError_t launch_precontract3(const Crystal &c, const Fc3Dev &f, const int *tar
 size_t rates3_lds_bytes(int nT);
 hipError_t launch_rates3(const Crystal &c, const Fc3Dev &f, const Rate3Args &a,
                          const double2 *U, int nblocks, hipStream_t s);
+
+// launcher (fp4_kappa.hip): kappa [nT][9] = scale * sum over modes of C v v tau
+hipError_t launch_kappa(const Crystal &c, const double *T, int nT, double hk, const double *occ,
+                        const double *r3, const double *r4, double scale, double kb,
+                        double *kappa, long long *skipped, hipStream_t s);
 
 // launchers (fp4_features.hip)
 hipError_t launch_fc4_strength(const Crystal &c, const int *targets, int nt, double *g4,

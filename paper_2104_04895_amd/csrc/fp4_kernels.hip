@@ -142,7 +142,7 @@ __global__ void k_occupations(const double *omega, int nmodes, const double *T, 
 // U[t][c][beta*9 + gamma*3 + theta] = sum_{n in combo c} sum_alpha Phi_n^{abgt}
 //                                     e^{lambda_t}_alpha(i_n)/sqrt(M) exp(i q.b_n)
 template <typename CR>
-__global__ void k_precontract(Crystal c, const int *targets, int nt, CR *U) {
+__global__ void k_precontract(Crystal c, const int *targets, int tbase, int nt, CR *U) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long total = (long long)nt * c.nc * 27;
   if (id >= total) return;
@@ -150,7 +150,7 @@ __global__ void k_precontract(Crystal c, const int *targets, int nt, CR *U) {
   const long long tc = id / 27;
   const int ci = (int)(tc % c.nc);
   const int t = (int)(tc / c.nc);
-  const int mu = targets[t];
+  const int mu = targets ? targets[t] : tbase + t;
   const int iq = mu / c.nb, j = mu % c.nb;
   const double2 *e1 = c.E64 + ((size_t)iq * c.nb + j) * c.nb;
   double2 acc = make_double2(0.0, 0.0);
@@ -401,8 +401,10 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
 // kept).  The two members of a mirror pair share |V| (V transposed), |v'' - v'''| and so
 // sigma, 1/(w'' w''') and the occupation factor; one evaluation serves both, each with its
 // own dw formed in its stand-alone order and its own Gaussian.  V is read from the group's
-// tile, (q''_g, q'''_g) from Gq.  Consecutive lanes take consecutive entries, so every lane
-// has work while the list lasts.
+// tile, (q''_g, q'''_g) from Gq (bit 30 of q'''_g: the block's processes are Umklapp ones).
+// Consecutive lanes take consecutive entries, so every lane has work while the list lasts.
+// With a.qclass == 3 the sums go by class instead of by channel: normal processes to
+// acc.r[0], Umklapp ones to acc.r[1] (adding 0.0 elsewhere leaves the other sums exact).
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const unsigned short *L, int cnt, int lane,
@@ -411,15 +413,16 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
   constexpr int S2 = (CH == 0) ? 1 : -1;
-  auto decode = [&](int i, int &mu2, int &mu3, int &vi, bool &pair) {
+  auto decode = [&](int i, int &mu2, int &mu3, int &vi, bool &pair, bool &umk) {
     const unsigned d = L[i];
     const int s = (int)(d >> 6), b = (int)(d & 63u);
     const int g = s / NB, r = s - g * NB;
     const int2 q = Gq[g];
+    umk = (q.y >> 30) != 0;
     const bool mir = b >= NB && b < 2 * NB;
     pair = b >= 2 * NB;
     const int cc = pair ? b - 2 * NB : (mir ? b - NB : b);
-    const int mr = q.x * NB + r, mc = q.y * NB + cc;
+    const int mr = q.x * NB + r, mc = (q.y & 0x3fffffff) * NB + cc;
     mu2 = mir ? mc : mr;
     mu3 = mir ? mr : mc;
     vi = g * xtile(NB, sizeof(CR)) + r * NB + cc;
@@ -427,8 +430,10 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
 #pragma unroll 1
   for (int i = lane; i < cnt; i += 64) {
     int mu2, mu3, vi;
-    bool pair;
-    decode(i, mu2, mu3, vi, pair);
+    bool pair, umk;
+    decode(i, mu2, mu3, vi, pair, umk);
+    const bool split = a.qclass == 3;
+    const bool sn = split && !umk, su = split && umk;
     const ModeRec<NT> p2 = load_rec<NB, NT>(c, a, mu2), p3 = load_rec<NB, NT>(c, a, mu3);
     double dw, s2, dwm = 0.0;
     window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
@@ -466,7 +471,18 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
         if (CH == 0) f = (1.0 + n1[t]) * (1.0 + n2) * n3;
         else if (CH == 1) f = (1.0 + n1[t]) * n2 * n3;
         else f = n1[t] * n2 * n3;
-        acc.r[CH][t] += p4 ? base : base * f * invn[t];
+        const double x = p4 ? base : base * f * invn[t];
+        if (CH == 0) {
+          acc.r[0][t] += su ? 0.0 : x;
+          acc.r[1][t] += su ? x : 0.0;
+        } else if (CH == 1) {
+          acc.r[1][t] += sn ? 0.0 : x;
+          acc.r[0][t] += sn ? x : 0.0;
+        } else {
+          acc.r[2][t] += split ? 0.0 : x;
+          acc.r[0][t] += sn ? x : 0.0;
+          acc.r[1][t] += su ? x : 0.0;
+        }
       }
     }
     acc.cnt[CH] += (CH == 1 && pair) ? 2 : 1;
@@ -480,9 +496,11 @@ constexpr int LSEG = 256;   // kept processes a wavefront evaluates per pass
 // of the q'' points.  Phase 1 compacts the blocks worth contracting into the wavefront's LDS
 // queue in a fixed order (ballot + prefix count): for ++ and -- the blocks with a surviving
 // process, for +- one block of every mirror pair {q'', q'''} (V of the pair members are
-// transposes of each other).  Phase 2 lets the wavefront's lane groups contract the queued
-// blocks densely (lane r of a group owns branch row j'' = r) and evaluates the kept
-// processes of the blocks in flight as one compacted list.
+// transposes of each other when the quartet list is symmetric under the slot-3/slot-4
+// exchange, a.mirror; otherwise every q'' block is queued and contracted on its own).
+// Phase 2 lets the wavefront's lane groups contract the queued blocks densely (lane r of a
+// group owns branch row j'' = r) and evaluates the kept processes of the blocks in flight as
+// one compacted list.
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs &a,
                                                const typename CT<R>::T *W, int wave, int lane,
@@ -499,6 +517,8 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   constexpr int S1 = (CH == 2) ? -1 : 1;
   constexpr int S2 = (CH == 0) ? 1 : -1;
   constexpr bool MIRROR = (CH == 1);
+  // mirror pairs share one contraction only for a slot-3/slot-4 symmetric quartet list
+  const bool mir = MIRROR && a.mirror != 0;
   constexpr double WCH = (CH == 2) ? (1.0 / 6.0) : 0.5;
   constexpr unsigned long long GMASK = (1ull << NB) - 1ull;
   const CR *Ws = W + (S1 > 0 ? 0 : c.ng * 9);
@@ -561,7 +581,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         const int cy = d2.y >= c.g1;
         d2.y -= cy ? c.g1 : 0;
         d2.z += DK.z + cy;
-        const bool lead = glane && iq2c < c.N && iq2c <= iq3c && r == 0;
+        const bool lead = glane && iq2c < c.N && (!mir || iq2c <= iq3c) && r == 0;
         const unsigned long long lb = __ballot(lead);
         if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
         cnt += __popcll(lb);
@@ -642,15 +662,16 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       wave_sync();
       if (act)
         row_bits_cols<NB, S2>(a, aw, c.mode4[iq2 * NB + r], c.qbound[iq3],
-                              reinterpret_cast<const double2 *>(Xg), MIRROR && iq2 != iq3, bA, bB);
+                              reinterpret_cast<const double2 *>(Xg), mir && iq2 != iq3, bA, bB);
+      bool umk = false;
       if (a.qclass != 0 && act) {
         // normal / Umklapp class of the block (the same for every branch and, for a mirror
         // pair, both orientations): Q = k(q''') - (k(q) + s' k(q') + s'' k(q'')) on the
         // first-zone image numerators of the four points
         const int4 k0 = c.qimg[mu / NB], k1 = c.qimg[mu1 / NB], k2 = c.qimg[iq2], k3 = c.qimg[iq3];
-        const bool umk = (k0.x + S1 * k1.x + S2 * k2.x != k3.x) || (k0.y + S1 * k1.y + S2 * k2.y != k3.y) ||
-                         (k0.z + S1 * k1.z + S2 * k2.z != k3.z);
-        if (umk != (a.qclass == 2)) {
+        umk = (k0.x + S1 * k1.x + S2 * k2.x != k3.x) || (k0.y + S1 * k1.y + S2 * k2.y != k3.y) ||
+              (k0.z + S1 * k1.z + S2 * k2.z != k3.z);
+        if (a.qclass != 3 && umk != (a.qclass == 2)) {
           bA = 0u;
           bB = 0u;
         }
@@ -664,7 +685,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
       }
-      if (act && r == 0) Gq[gw] = make_int2(iq2, iq3);
+      if (act && r == 0) Gq[gw] = make_int2(iq2, iq3 | (umk ? (1 << 30) : 0));
       // the lane's list entries: single orientations, then mirror pairs with both kept
       // (codes as in gamma_list); their place in the wavefront's list is a prefix sum of the
       // per-lane counts (<= 2 NB < 32) by bit-sliced ballots
@@ -731,7 +752,7 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
   for (int i = tid; i < c.ng; i += 256) sg_d[i] = c.g_d[i];
   for (int i = tid; i <= c.nat * c.nat; i += 256) skl[i] = c.kl_start[i];
 
-  const int mu = a.targets[t];
+  const int mu = a.targets ? a.targets[t] : a.tbase + t;
   const int iq = mu / NB;
   Acc<NT> acc;
 #pragma unroll
@@ -883,27 +904,29 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 && NB <= 6) ? 4 : 3) void k_ra
   }
 }
 
-// ordered reduction over q'-chunks: rates[T][t], per channel, counts
+// ordered reduction over q'-chunks of targets 0 .. nt-1 of the partial buffers:
+// rates[T][off + t] (row stride `stride`), per channel, counts
 __global__ void k_reduce(const double *partial, const unsigned long long *pcount, int nt,
-                         int nchunk, int nT, double *rates, double *rates_ch,
-                         long long *counts) {
+                         int nchunk, int nT, int stride, int off, double *rates,
+                         double *rates_ch, long long *counts) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
+  const size_t o = (size_t)off + t;
   for (int tt = 0; tt < nT; ++tt) {
     double tot = 0.0;
     for (int ch = 0; ch < 3; ++ch) {
       double s = 0.0;
       for (int k = 0; k < nchunk; ++k) s += partial[(((size_t)t * nchunk + k) * 3 + ch) * nT + tt];
-      if (rates_ch) rates_ch[((size_t)tt * 3 + ch) * nt + t] = s;
+      if (rates_ch) rates_ch[((size_t)tt * 3 + ch) * stride + o] = s;
       tot += s;
     }
-    rates[(size_t)tt * nt + t] = tot;
+    rates[(size_t)tt * stride + o] = tot;
   }
   if (counts)
     for (int ch = 0; ch < 3; ++ch) {
       unsigned long long s = 0;
       for (int k = 0; k < nchunk; ++k) s += pcount[((size_t)t * nchunk + k) * 3 + ch];
-      counts[(size_t)t * 3 + ch] = (long long)s;
+      counts[o * 3 + ch] = (long long)s;
     }
 }
 
@@ -1033,17 +1056,21 @@ hipError_t launch_occupations(const Crystal &c, const double *T, int nT, double 
 }
 
 hipError_t launch_precontract(const Crystal &c, const int *targets, int nt, int fp32, void *U,
-                              hipStream_t s) {
+                              hipStream_t s, int tbase) {
   const long long total = (long long)nt * c.nc * 27;
   const int nthr = 256;
   const unsigned grid = (unsigned)((total + nthr - 1) / nthr);
   if (fp32)
-    hipLaunchKernelGGL(k_precontract<float2>, dim3(grid), dim3(nthr), 0, s, c, targets, nt,
+    hipLaunchKernelGGL(k_precontract<float2>, dim3(grid), dim3(nthr), 0, s, c, targets, tbase, nt,
                        reinterpret_cast<float2 *>(U));
   else
-    hipLaunchKernelGGL(k_precontract<double2>, dim3(grid), dim3(nthr), 0, s, c, targets, nt,
+    hipLaunchKernelGGL(k_precontract<double2>, dim3(grid), dim3(nthr), 0, s, c, targets, tbase, nt,
                        reinterpret_cast<double2 *>(U));
   return hipGetLastError();
+}
+
+size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT) {
+  return rate_lds_bytes(c, fp32, nT <= 1 ? 1 : nT <= 2 ? 2 : nT <= 4 ? 4 : 8);
 }
 
 hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream_t s) {
@@ -1105,9 +1132,14 @@ hipError_t launch_batch(const BatchInst *insts, int ninst, long long total,
 }
 hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double *rates_ch,
                          long long *counts, hipStream_t s) {
+  return launch_reduce_strided(a, nt_total, nt_total, 0, rates, rates_ch, counts, s);
+}
+
+hipError_t launch_reduce_strided(const RateArgs &a, int nt, int stride, int off, double *rates,
+                                 double *rates_ch, long long *counts, hipStream_t s) {
   const int nthr = 128;
-  hipLaunchKernelGGL(k_reduce, dim3((nt_total + nthr - 1) / nthr), dim3(nthr), 0, s,
-                     a.partial, a.pcount, nt_total, a.nchunk, a.nT, rates, rates_ch, counts);
+  hipLaunchKernelGGL(k_reduce, dim3((nt + nthr - 1) / nthr), dim3(nthr), 0, s, a.partial,
+                     a.pcount, nt, a.nchunk, a.nT, stride, off, rates, rates_ch, counts);
   return hipGetLastError();
 }
 

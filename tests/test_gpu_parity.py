@@ -465,3 +465,80 @@ def test_large_grid_properties(fp4):
     assert np.array_equal(c1, c2) and np.array_equal(c32, c1)
     np.testing.assert_allclose(r2, r1, rtol=1e-12)
     assert _rel(r32, r1) <= RTOL32
+
+
+def test_normal_umklapp_split_even_fcc_grid(fp4):
+    """Normal / Umklapp classes on the even 4x4x4 diamond grid, whose L, X and W points sit on
+    the zone boundary (equally short first-zone images, the tie reading of the split): every
+    mode, both classes against the oracle's class sums (counts exact, FP64 1e-10, FP32 1e-4)."""
+    _say("case: normal/Umklapp split, 4x4x4 diamond")
+    inst = synth.diamond_instance((4, 4, 4), synth.configs.RC_FIRST, seed=12, T=(300.0, 800.0))
+    m = oracle.Model.from_instance(inst)
+    dq = oracle.default_dq(inst.cr.A, inst.grid)
+    refs = [oracle.rates4_class(m, inst.cr.A, cls, inst.T, 1.0, 7, dq) for cls in (1, 2)]
+    with _ctx(fp4, inst) as c:
+        for cls in (1, 2):
+            c.set_param(fp4.FP4_PARAM_QCLASS, cls)
+            r, _, cnt = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+            r32, _, cnt32 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP32)
+            r_o, _, c_o = refs[cls - 1]
+            assert c_o.sum() > 0
+            assert np.array_equal(cnt, c_o) and np.array_equal(cnt32, c_o)
+            assert _rel(r, r_o) <= RTOL64
+            assert _rel(r32, r_o) <= RTOL32
+        # both classes from one pass (the QCLASS setting is ignored by this call)
+        for prec, tol in ((fp4.FP4_FP64, RTOL64), (fp4.FP4_FP32, RTOL32)):
+            r, rn, ru, cnt = c.compute_rates4_classes(inst.T, 1.0, 7, prec)
+            assert np.array_equal(cnt, refs[0][2] + refs[1][2])
+            assert _rel(rn, refs[0][0]) <= tol and _rel(ru, refs[1][0]) <= tol
+            assert _rel(r, refs[0][0] + refs[1][0]) <= tol
+            assert _rel(rn + ru, r) <= 1e-12
+
+
+def test_asymmetric_quartet_list(fp4, small):
+    """A quartet list that is not symmetric under the slot-3/slot-4 exchange (random noise
+    added to 10 quartets): the redistribution matrix element is then not symmetric in
+    lambda'' and lambda''', so the mirror-pair shortcut must be off.  Rates of every mode
+    against Eq. V4 evaluated literally by the oracle, redistribution only and all channels."""
+    _say("case: asymmetric quartet list, 3x3x3")
+    rng = np.random.default_rng(21)
+    phi = small.fc4.phi.copy()
+    pick = rng.choice(phi.shape[0], 10, replace=False)
+    phi[pick] += rng.standard_normal((10, 81)) * np.abs(phi).max()
+    mo = oracle.Model(small.grid, small.cr.mass, small.omega, small.evec, small.vel,
+                      small.fc4.atoms, small.fc4.cells, phi)
+    dq = oracle.default_dq(small.cr.A, small.grid)
+    with fp4.Context(0) as c:
+        c.load_lattice(small.cr.A, small.grid, small.cr.mass, dq)
+        c.load_modes(small.omega, small.evec, small.vel)
+        c.load_fc4(small.fc4.atoms, small.fc4.cells, phi)
+        for mask in (fp4.FP4_PM, 7):
+            r_o, _, c_o = oracle.rates4(mo, small.T, 1.0, mask, dq)
+            r, _, cnt = c.compute_rates4(small.T, 1.0, mask, fp4.FP4_FP64)
+            r32, _, cnt32 = c.compute_rates4(small.T, 1.0, mask, fp4.FP4_FP32)
+            assert np.array_equal(cnt, c_o) and np.array_equal(cnt32, c_o)
+            assert _rel(r, r_o) <= RTOL64
+            assert _rel(r32, r_o) <= RTOL32
+
+
+def test_injected_allocation_failure(fp4, small, monkeypatch):
+    """FP4_TEST_FAIL_ALLOC=k makes the k-th device allocation of a context fail: the load that
+    hits it returns FP4_E_NOMEM with a message, the context stays usable, and repeating the
+    load then gives the same rates as an undisturbed context."""
+    _say("case: injected allocation failure")
+    with _ctx(fp4, small) as c:
+        ref, _, ref_c = c.compute_rates4(small.T, 1.0, 7, fp4.FP4_FP64)
+    monkeypatch.setenv("FP4_TEST_FAIL_ALLOC", "3")
+    with fp4.Context(0) as c:
+        monkeypatch.delenv("FP4_TEST_FAIL_ALLOC")
+        dq = oracle.default_dq(small.cr.A, small.grid)
+        c.load_lattice(small.cr.A, small.grid, small.cr.mass, dq)      # allocation 1
+        with pytest.raises(fp4.Fp4Error) as e:
+            c.load_modes(small.omega, small.evec, small.vel)          # allocations 2, 3, 4
+        assert e.value.code == fp4.FP4_E_NOMEM
+        assert "FP4_TEST_FAIL_ALLOC" in str(e.value)
+        c.load_modes(small.omega, small.evec, small.vel)
+        c.load_fc4(small.fc4.atoms, small.fc4.cells, small.fc4.phi)
+        r, _, cnt = c.compute_rates4(small.T, 1.0, 7, fp4.FP4_FP64)
+    assert np.array_equal(cnt, ref_c)
+    assert np.array_equal(r, ref)
