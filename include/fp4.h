@@ -200,6 +200,25 @@ int fp4_compute_rates4_async(fp4_ctx *ctx, const double *T, int32_t nT, double s
                              uint32_t mask, int32_t precision, void *hip_stream,
                              double *d_rates, double *d_rates_by_channel, int64_t *d_counts);
 
+/* Allocation-free form of fp4_compute_rates4_async, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and outputs as fp4_compute_rates4_async (every mode of the grid, device
+ * outputs, work enqueued on hip_stream, returns without waiting).  It calls no hipMalloc,
+ * hipFree or other allocating routine: its intermediates (occupations, precontraction,
+ * partial sums) live in a fixed scratch area of 64 MiB per GPU, a device array of the library
+ * held until the process ends, and the targets are processed in batches that fit it.
+ *   - the loads must have completed (they build the per-q tables), else FP4_E_STATE;
+ *   - 2 nT nq nb doubles of occupations plus one target's precontraction and partial sums
+ *     must fit the 64 MiB, else FP4_E_UNSUPPORTED (the message gives the size needed);
+ *   - every call on one GPU shares that GPU's scratch area, which keeps the last call's
+ *     contents: calls that overlap on one GPU (other streams or host threads, any context)
+ *     race and must be serialised by the caller;
+ *   - fp4_last_stats and fp4_last_timing are not updated.
+ * The results equal those of fp4_compute_rates4_async with the same q'-chunk. */
+int fp4_compute_rates4_noalloc(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                               uint32_t mask, int32_t precision, void *hip_stream,
+                               double *d_rates, double *d_rates_by_channel, int64_t *d_counts);
+
 /* Matrix elements V of Eq. V4 through the library's own contraction path.
  *   quads [n][8] = (iq, j, iq', j', iq'', j'', j''', channel) with channel 0 (++), 1 (+-),
  *                  2 (--); iq''' is q + s' q' + s'' q'' folded into the grid

@@ -44,7 +44,7 @@ EXPORTED = [
     "fp4_mlp_last_error", "fp4_mlp_num_params", "fp4_mlp_get_params", "fp4_mlp_set_params",
     "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict", "fp4_load_fc3",
     "fp4_compute_rates3", "fp4_surrogate_features", "fp4_compute_rates4_wedge",
-    "fp4_compute_rates4_classes", "fp4_compute_kappa_rta",
+    "fp4_compute_rates4_classes", "fp4_compute_rates4_noalloc", "fp4_compute_kappa_rta",
 ]
 FP4_NFEAT = 18
 
@@ -89,6 +89,7 @@ def lib():
         L.fp4_compute_rates4_classes.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P, P]
         L.fp4_compute_kappa_rta.argtypes = [P, P, i32, f64, i32, P, P, P, P]
         L.fp4_compute_rates4_async.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
+        L.fp4_compute_rates4_noalloc.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
         L.fp4_debug_matrix_elements.argtypes = [P, i32, P, i32, P]
         L.fp4_last_stats.argtypes = [P, P, P, P]
         L.fp4_last_timing.argtypes = [P, P, P]
@@ -316,6 +317,18 @@ class Context:
                                               ctypes.c_void_p(d_rates_ch or None),
                                               ctypes.c_void_p(d_counts or None))
         self._check(rc, "fp4_compute_rates4_async")
+
+    def compute_rates4_noalloc(self, T, scalebroad, mask, precision, stream_ptr, d_rates,
+                               d_rates_ch=0, d_counts=0):
+        """Allocation-free device-pointer form (the library's fixed scratch area)."""
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        rc = self._L.fp4_compute_rates4_noalloc(self._h, _p(T), len(T), float(scalebroad),
+                                                int(mask), int(precision),
+                                                ctypes.c_void_p(stream_ptr),
+                                                ctypes.c_void_p(d_rates),
+                                                ctypes.c_void_p(d_rates_ch or None),
+                                                ctypes.c_void_p(d_counts or None))
+        self._check(rc, "fp4_compute_rates4_noalloc")
 
     def debug_matrix_elements(self, quads, precision=FP4_FP64):
         q = np.ascontiguousarray(quads, dtype=np.int32).reshape(-1, 8)

@@ -541,6 +541,13 @@ int fp4_create(fp4_ctx **out, int device_id) {
     delete ctx;
     return FP4_E_DEVICE;
   }
+  // address of this device's allocation-free scratch area (looked up once per device)
+  if (fp4::scratch_init(device_id, nullptr) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return FP4_E_DEVICE;
+  }
   if (const char *f = std::getenv("FP4_TEST_FAIL_ALLOC")) ctx->fail_alloc_at = std::atoi(f);
   *out = ctx;
   return FP4_OK;
@@ -1029,6 +1036,90 @@ int fp4_compute_rates4_async(fp4_ctx *ctx, const double *T, int32_t nT, double s
   } catch (const std::bad_alloc &) {
     return ctx->fail(FP4_E_NOMEM, "host allocation failed");
   }
+}
+
+int fp4_compute_rates4_noalloc(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                               uint32_t mask, int32_t precision, void *hip_stream,
+                               double *d_rates, double *d_rates_by_channel, int64_t *d_counts) {
+  if (!ctx) return FP4_E_INVAL;
+  int rc = check_compute_args(ctx, T, nT, scalebroad, mask, precision);
+  if (rc) return rc;
+  if (!d_rates) return ctx->fail(FP4_E_INVAL, "d_rates is required");
+  if (ctx->tables_dirty)
+    return ctx->fail(FP4_E_STATE, "the per-q tables are not built (a load did not complete)");
+  (void)hipSetDevice(ctx->device);
+  unsigned char *base = static_cast<unsigned char *>(fp4::scratch_ptr(ctx->device));
+  if (!base) return ctx->fail(FP4_E_DEVICE, "the scratch area of this device was not found");
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const int fp32 = precision == FP4_FP32;
+  const size_t nmodes = (size_t)ctx->N * ctx->nb;
+  int qchunk = ctx->qchunk > 0 ? ctx->qchunk : auto_qchunk(ctx, (int)nmodes, nT);
+  if (qchunk > ctx->N) qchunk = ctx->N;
+  const int nchunk = (ctx->N + qchunk - 1) / qchunk;
+  const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  // scratch layout: occupations, 1/occupations, block counter, then per target batch the
+  // precontraction U, the partial rates and the partial counts
+  const size_t b_occ = up(nmodes * nT * sizeof(double)), b_blk = 256;
+  const size_t fixed = 2 * b_occ + b_blk;
+  const size_t u_t = (size_t)ctx->nc * 27 * cb;
+  const size_t p_t = (size_t)nchunk * 3 * nT * sizeof(double);
+  const size_t c_t = (size_t)nchunk * 3 * sizeof(unsigned long long);
+  const size_t need1 = fixed + up(u_t) + up(p_t) + up(c_t);
+  if (need1 > fp4::kScratchBytes)
+    return ctx->fail(FP4_E_UNSUPPORTED, "the allocation-free call needs " + std::to_string(need1) +
+                                            " bytes of scratch for these sizes; its scratch area holds " +
+                                            std::to_string(fp4::kScratchBytes) + " bytes");
+  size_t batch = (fp4::kScratchBytes - fixed - 3 * 256) / (u_t + p_t + c_t);
+  batch = std::min<size_t>(batch, nmodes);
+  batch = std::min<size_t>(batch, (size_t)(((1ll << 31) - 1) / nchunk));
+  double *occ = reinterpret_cast<double *>(base);
+  double *iocc = reinterpret_cast<double *>(base + b_occ);
+  unsigned long long *blocks = reinterpret_cast<unsigned long long *>(base + 2 * b_occ);
+  void *U = base + fixed;
+  double *partial = reinterpret_cast<double *>(base + fixed + up(batch * u_t));
+  unsigned long long *pcount =
+      reinterpret_cast<unsigned long long *>(base + fixed + up(batch * u_t) + up(batch * p_t));
+  fp4::Crystal c = make_crystal(ctx);
+  FP4_HIP(ctx, fp4::launch_zero(blocks, sizeof(unsigned long long), s));
+  FP4_HIP(ctx, fp4::launch_occupations_v(c, T, nT, hbar_over_kb_kps(), occ, iocc, s));
+  fp4::RateArgs a{};
+  const double wsb = ctx->window_w * scalebroad;
+  a.c_win = (wsb * ctx->dq) * (wsb * ctx->dq);
+  a.sqrt_c_win = wsb * ctx->dq;
+  a.c_sig = (scalebroad * ctx->dq) * (scalebroad * ctx->dq);
+  a.c_min = ctx->sigma_min * ctx->sigma_min;
+  a.kpref = (ctx->harmonic ? 1.0 : c4_prefactor()) / ((double)ctx->N * (double)ctx->N);
+  a.harmonic = ctx->harmonic;
+  a.mirror = ctx->sym34 ? 1 : 0;
+  a.nT = nT;
+  a.mask = mask;
+  a.qclass = ctx->qclass;
+  a.occ = occ;
+  a.inv_occ = iocc;
+  a.targets = nullptr;
+  a.qchunk = qchunk;
+  a.nchunk = nchunk;
+  a.nxcd = kXcds;
+  a.U = U;
+  a.partial = partial;
+  a.pcount = pcount;
+  a.blocks = blocks;
+  a.t0 = 0;
+  for (size_t t0 = 0; t0 < nmodes; t0 += batch) {
+    const int nb_t = (int)std::min(batch, nmodes - t0);
+    a.tbase = (int)t0;
+    a.nt = nb_t;
+    FP4_HIP(ctx, fp4::launch_precontract(c, nullptr, nb_t, fp32, U, s, (int)t0));
+    const hipError_t le = fp4::launch_rates(c, a, fp32, s);
+    if (le == hipErrorInvalidValue)
+      return ctx->fail(FP4_E_UNSUPPORTED, "the quartet list needs more LDS than a work-group has (too many atom-pair groups for this branch count)");
+    FP4_HIP(ctx, le);
+    FP4_HIP(ctx, fp4::launch_reduce_strided(a, nb_t, (int)nmodes, (int)t0, d_rates,
+                                            d_rates_by_channel, (long long *)d_counts, s));
+  }
+  ctx->err.clear();
+  return FP4_OK;
 }
 
 int fp4_debug_matrix_elements(fp4_ctx *ctx, int32_t n, const int32_t *quads, int32_t precision,

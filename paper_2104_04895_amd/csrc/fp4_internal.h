@@ -127,11 +127,21 @@ hipError_t launch_occupations(const Crystal &c, const double *T, int nT, double 
                               double *occ, double *inv_occ, hipStream_t s);
 hipError_t launch_precontract(const Crystal &c, const int *targets, int nt, int fp32,
                               void *U, hipStream_t s, int tbase = 0);
+// n0 and 1/n0 with the temperatures passed by value (no device copy of T)
+hipError_t launch_occupations_v(const Crystal &c, const double *T, int nT, double hbar_over_kb,
+                                double *occ, double *inv_occ, hipStream_t s);
 // ordered reduction writing rates [nT][stride] (and per channel [nT][3][stride]) at columns
 // off .. off + nt - 1, counts [stride][3] at rows off ..
 hipError_t launch_reduce_strided(const RateArgs &a, int nt, int stride, int off, double *rates,
                                  double *rates_ch, long long *counts, hipStream_t s);
 size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT);
+
+// Allocation-free scratch area: a file-scope device array of kScratchBytes per GPU.
+// scratch_init() looks up its address on the current device (once per device) and returns
+// it; scratch_ptr(dev) returns the address found for device dev (null before the lookup).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t scratch_init(int dev, void **out);
+void *scratch_ptr(int dev);
 hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream_t s);
 hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double *rates_ch,
                          long long *counts, hipStream_t s);

@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 namespace fp4 {
 namespace {
 
@@ -122,7 +124,32 @@ __global__ void k_tables(Crystal c, double4 *qbound, double4 *mode4, double *inv
   }
 }
 
+// temperatures passed by value
+struct TempList {
+  double T[8];
+};
+
 // n0 = 1/expm1(hbar w / k T) (after Eq. 4phgamma); 1/n0 = expm1(.)  (0 for inactive modes)
+__global__ void k_occupations_v(const double *omega, int nmodes, TempList T, int nT, double hk,
+                                double *occ, double *inv_occ) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nmodes * nT) return;
+  const int t = i / nmodes, m = i % nmodes;
+  const double w = omega[m];
+  double Tt = T.T[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (k == t) Tt = T.T[k];
+  if (w > 0.0) {
+    const double em = expm1(hk * w / Tt);
+    occ[i] = 1.0 / em;
+    inv_occ[i] = em;
+  } else {
+    occ[i] = 0.0;
+    inv_occ[i] = 0.0;
+  }
+}
+
 __global__ void k_occupations(const double *omega, int nmodes, const double *T, int nT,
                               double hk, double *occ, double *inv_occ) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -930,6 +957,11 @@ __global__ void k_reduce(const double *partial, const unsigned long long *pcount
     }
 }
 
+// Scratch area of the allocation-free entry point (kScratchBytes per GPU, held while the
+// process lives).  Host code never uses this name as an address: the device address comes
+// from hipGetSymbolAddress (scratch_init) and is kept per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 // V for explicit processes through the same W'' build and branch-block contraction.
 // One wavefront per process; lanes 0..NB-1 form the group.
 template <typename R, int NB>
@@ -1069,8 +1101,46 @@ hipError_t launch_precontract(const Crystal &c, const int *targets, int nt, int 
   return hipGetLastError();
 }
 
+hipError_t launch_occupations_v(const Crystal &c, const double *T, int nT, double hk,
+                                double *occ, double *inv_occ, hipStream_t s) {
+  if (nT < 1 || nT > 8) return hipErrorInvalidValue;
+  TempList tl{};
+  for (int i = 0; i < nT; ++i) tl.T[i] = T[i];
+  const int n = c.N * c.nb * nT, nthr = 256;
+  hipLaunchKernelGGL(k_occupations_v, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, c.omega,
+                     c.N * c.nb, tl, nT, hk, occ, inv_occ);
+  return hipGetLastError();
+}
+
 size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT) {
   return rate_lds_bytes(c, fp32, nT <= 1 ? 1 : nT <= 2 ? 2 : nT <= 4 ? 4 : 8);
+}
+
+namespace {
+void *g_scratch[64];
+bool g_scratch_done[64];
+std::mutex g_scratch_mu;
+}  // namespace
+
+hipError_t scratch_init(int dev, void **out) {
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void *p = nullptr;
+    // the caller has made `dev` the current device
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = p;
+    g_scratch_done[dev] = true;
+  }
+  if (out) *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+void *scratch_ptr(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[dev];
 }
 
 hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream_t s) {
