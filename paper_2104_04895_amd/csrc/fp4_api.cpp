@@ -89,7 +89,7 @@ struct fp4_ctx {
 
   // device buffers
   DevBuf d_omega, d_iw, d_m4, d_qbnd, d_vel, d_evec, d_mass, d_E64, d_E32, d_qn, d_PHA64, d_PHB64, d_PHD64, d_PHD32;
-  DevBuf d_qord, d_qordw, d_qimg;
+  DevBuf d_qord, d_qordw, d_qimg, d_speed;
   std::vector<int> h_qimg;
   int qclass = 0, harmonic = 0;
   // the quartet list is symmetric under the exchange of slots 3 and 4 (see fp4_load_fc4)
@@ -181,6 +181,7 @@ fp4::Crystal make_crystal(const fp4_ctx *ctx) {
   c.inv_omega = (const double *)ctx->d_iw.p;
   c.vel = (const double4 *)ctx->d_vel.p;
   c.mode4 = (const double4 *)ctx->d_m4.p;
+  c.speed = (const double *)ctx->d_speed.p;
   c.qbound = (const double4 *)ctx->d_qbnd.p;
   c.qimg = (const int4 *)ctx->d_qimg.p;
   c.qord = (const int4 *)ctx->d_qord.p;
@@ -214,6 +215,7 @@ int ensure_tables(fp4_ctx *ctx) {
   int rc;
   if ((rc = ensure(ctx, ctx->d_iw, N * nb * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->d_m4, N * nb * sizeof(double4)))) return rc;
+  if ((rc = ensure(ctx, ctx->d_speed, N * nb * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->d_qbnd, N * sizeof(double4)))) return rc;
   if ((rc = ensure(ctx, ctx->d_E64, N * nb * nb * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx, ctx->d_E32, N * nb * nb * sizeof(float2)))) return rc;
@@ -223,7 +225,7 @@ int ensure_tables(fp4_ctx *ctx) {
   if ((rc = ensure(ctx, ctx->d_PHD64, N * ctx->nd * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx, ctx->d_PHD32, N * ctx->nd * sizeof(float2)))) return rc;
   fp4::Crystal c = make_crystal(ctx);
-  FP4_HIP(ctx, fp4::launch_tables(c, (double4 *)ctx->d_qbnd.p, (double4 *)ctx->d_m4.p, (double *)ctx->d_iw.p, (double2 *)ctx->d_E64.p, (float2 *)ctx->d_E32.p,
+  FP4_HIP(ctx, fp4::launch_tables(c, (double4 *)ctx->d_qbnd.p, (double4 *)ctx->d_m4.p, (double *)ctx->d_speed.p, (double *)ctx->d_iw.p, (double2 *)ctx->d_E64.p, (float2 *)ctx->d_E32.p,
                                   (const double *)ctx->d_evec.p, (const double *)ctx->d_mass.p,
                                   (int4 *)ctx->d_qn.p, (double2 *)ctx->d_PHA64.p,
                                   (double2 *)ctx->d_PHB64.p, (double2 *)ctx->d_PHD64.p,
@@ -557,7 +559,7 @@ void fp4_destroy(fp4_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_qbnd, &ctx->d_qord, &ctx->d_qordw, &ctx->d_qimg, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
+  DevBuf *all[] = {&ctx->d_omega, &ctx->d_iw, &ctx->d_m4, &ctx->d_speed, &ctx->d_qbnd, &ctx->d_qord, &ctx->d_qordw, &ctx->d_qimg, &ctx->d_vel, &ctx->d_evec, &ctx->d_mass, &ctx->d_E64,
                    &ctx->d_E32, &ctx->d_qn, &ctx->d_PHA64, &ctx->d_PHB64, &ctx->d_PHD64,
                    &ctx->d_PHD32, &ctx->d_g_d, &ctx->d_kl, &ctx->d_cs, &ctx->d_cj, &ctx->d_ca,
                    &ctx->d_cq, &ctx->d_qi, &ctx->d_qb, &ctx->d_qphi, &ctx->d_avec, &ctx->d_bvec,

@@ -24,6 +24,7 @@ struct Crystal {
   const double *inv_omega;  // [N*nb] 1/omega (0 for inactive modes)
   const double4 *vel;       // [N*nb] (x, y, z, 0)
   const double4 *mode4;     // [N*nb] (vx, vy, vz, omega)
+  const double *speed;      // [N*nb] |v|
   const double4 *qbound;    // [N] (min omega, max omega, max |v|, 0) of the active branches
   const int4 *qimg;         // [N] first-zone image of each q: n_d + m_d N_d per axis
   const int4 *qord;         // [N] (iq, n1, n2, n3) of the q points in ascending qbound.x
@@ -119,7 +120,7 @@ struct Rate3Args {
 };
 
 // launchers (fp4_kernels.hip)
-hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
+hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *speed, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec, hipStream_t s);

@@ -72,7 +72,7 @@ __host__ __device__ constexpr int xtile(int nb, int cbytes) {
 
 // ------------------------------------------------------------------ table kernels
 
-__global__ void k_tables(Crystal c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
+__global__ void k_tables(Crystal c, double4 *qbound, double4 *mode4, double *speed, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec) {
@@ -86,6 +86,7 @@ __global__ void k_tables(Crystal c, double4 *qbound, double4 *mode4, double *inv
     inv_omega[(size_t)iq * nb + j] = w > 0.0 ? 1.0 / w : 0.0;
     const double4 v = c.vel[(size_t)iq * nb + j];
     mode4[(size_t)iq * nb + j] = make_double4(v.x, v.y, v.z, w);
+    speed[(size_t)iq * nb + j] = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
   }
   // frequency range and largest speed of the active branches at this q (an empty range,
   // w_min > w_max, when no branch is active)
@@ -373,14 +374,18 @@ struct Acc {
 // branches) and a kept process needs |dw| <= sqrt(c_win) |v'' - v'''| <= sqrt(c_win)
 // (|v_row| + v_max(q''')); the bound is applied with a relative margin of 1e-6, far above
 // FP64 rounding, so it never drops a process the exact test would keep.
+//
+// The two orientations of a mirror row share s2: d = v'' - v''' of one is the negative of the
+// other's, so their squares and s2 = (dx*dx + dy*dy) + dz*dz are bitwise equal, and only dw
+// is formed twice, each in its own stand-alone order.
 template <int NB, int S2>
 __device__ __forceinline__ void row_bits_cols(const RateArgs &a, double aw, const double4 vr,
-                                              const double4 qb, const double2 *cs,
+                                              double speed, const double4 qb, const double2 *cs,
                                               bool mirror_row, unsigned &b0, unsigned &b1) {
+#pragma clang fp contract(off)
   b0 = 0u;
   b1 = 0u;
   if (!(vr.w > 0.0)) return;
-  const double speed = sqrt(vr.x * vr.x + vr.y * vr.y + vr.z * vr.z);
   const double lim = a.sqrt_c_win * (speed + qb.z) * (1.0 + 1e-6) + 1e-12;
   auto dist = [&](double x) {
     const double lo = x - qb.y, hi = x - qb.x;
@@ -394,10 +399,17 @@ __device__ __forceinline__ void row_bits_cols(const RateArgs &a, double aw, cons
   for (int cc = 0; cc < NB; ++cc) {
     const double2 p0 = cs[2 * cc], p1 = cs[2 * cc + 1];
     const double4 vc = make_double4(p0.x, p0.y, p1.x, p1.y);
-    double dw, s2;
     if (vc.w > 0.0) {
-      if (t0 && window_keep(bw, vc.w, vr, vc, a.c_win, dw, s2)) b0 |= 1u << cc;
-      if (t1 && window_keep(add_signed(aw, vc.w, S2), vr.w, vc, vr, a.c_win, dw, s2)) b1 |= 1u << cc;
+      const double dx = vr.x - vc.x, dy = vr.y - vc.y, dz = vr.z - vc.z;
+      const double lim2 = a.c_win * ((dx * dx + dy * dy) + dz * dz);
+      if (t0) {
+        const double dw = bw - vc.w;
+        if (dw * dw <= lim2) b0 |= 1u << cc;
+      }
+      if (t1) {
+        const double dw = add_signed(aw, vc.w, S2) - vr.w;
+        if (dw * dw <= lim2) b1 |= 1u << cc;
+      }
     }
   }
 }
@@ -460,7 +472,6 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
     bool pair, umk;
     decode(i, mu2, mu3, vi, pair, umk);
     const bool split = a.qclass == 3;
-    const bool sn = split && !umk, su = split && umk;
     const ModeRec<NT> p2 = load_rec<NB, NT>(c, a, mu2), p3 = load_rec<NB, NT>(c, a, mu3);
     double dw, s2, dwm = 0.0;
     window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
@@ -483,8 +494,16 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       double y = __builtin_amdgcn_rsq(sig2);
       y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
       y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
-      delta = exp(-(dw * dw) * (y * y)) * (0.5641895835477563 * y);
-      if (CH == 1 && pair) delta += exp(-(dwm * dwm) * (y * y)) * (0.5641895835477563 * y);
+      const double y2 = y * y, x0 = (dw * dw) * y2;
+      const double e0 = exp(-x0);
+      delta = e0 * (0.5641895835477563 * y);
+      if (CH == 1 && pair) {
+        // the mirrored member's exponent differs from x0 only by the rounding of its dw
+        // (|x0 - x1| <= 1e-8 for any sigma above the floor), so exp(-x1) =
+        // e0 exp(d) = e0 (1 + d + d^2/2) to far below the FP64 rounding, d = x0 - x1
+        const double d = x0 - (dwm * dwm) * y2;
+        delta += fma(e0, fma(0.5 * d, d, d), e0) * (0.5641895835477563 * y);
+      }
     }
     // P4 (harmonic 2): channel weight / N^2 times delta only
     const bool p4 = a.harmonic == 2;
@@ -499,16 +518,11 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
         else if (CH == 1) f = (1.0 + n1[t]) * n2 * n3;
         else f = n1[t] * n2 * n3;
         const double x = p4 ? base : base * f * invn[t];
-        if (CH == 0) {
-          acc.r[0][t] += su ? 0.0 : x;
-          acc.r[1][t] += su ? x : 0.0;
-        } else if (CH == 1) {
-          acc.r[1][t] += sn ? 0.0 : x;
-          acc.r[0][t] += sn ? x : 0.0;
+        if (split) {
+          if (umk) acc.r[1][t] += x;
+          else acc.r[0][t] += x;
         } else {
-          acc.r[2][t] += split ? 0.0 : x;
-          acc.r[0][t] += sn ? x : 0.0;
-          acc.r[1][t] += su ? x : 0.0;
+          acc.r[CH][t] += x;
         }
       }
     }
@@ -625,6 +639,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       bool live = glane && p < nscan;
       const double4 z4 = make_double4(0.0, 0.0, 0.0, 0.0);
       double4 vr = live ? c.mode4[iq2 * NB + r] : z4;
+      double sp = live ? c.speed[iq2 * NB + r] : 0.0;
       double4 qb = live ? c.qbound[iq3] : z4;
       double4 vc = live ? c.mode4[iq3 * NB + r] : z4;
       double2 *cs = reinterpret_cast<double2 *>(Xg);
@@ -632,6 +647,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         const bool livec = live;
         const int iq2c = iq2;
         const double4 vrc = vr, qbc = qb;
+        const double spc = sp;
         // lane r holds column record r of the round; the group shares the six through its tile
         if (livec) {
           cs[2 * r] = make_double2(vc.x, vc.y);
@@ -644,6 +660,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         live = glane && k + 1 < k1 && p < nscan;
         if (live) {
           vr = c.mode4[iq2 * NB + r];
+          sp = c.speed[iq2 * NB + r];
           qb = c.qbound[iq3];
           vc = c.mode4[iq3 * NB + r];
         }
@@ -651,7 +668,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         bool keep = false;
         if (livec) {
           unsigned b0, b1;
-          row_bits_cols<NB, S2>(a, aw, vrc, qbc, cs, false, b0, b1);
+          row_bits_cols<NB, S2>(a, aw, vrc, spc, qbc, cs, false, b0, b1);
           const unsigned long long bal = __ballot(b0 != 0u);
           keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
         }
@@ -688,7 +705,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       }
       wave_sync();
       if (act)
-        row_bits_cols<NB, S2>(a, aw, c.mode4[iq2 * NB + r], c.qbound[iq3],
+        row_bits_cols<NB, S2>(a, aw, c.mode4[iq2 * NB + r], c.speed[iq2 * NB + r], c.qbound[iq3],
                               reinterpret_cast<const double2 *>(Xg), mir && iq2 != iq3, bA, bB);
       bool umk = false;
       if (a.qclass != 0 && act) {
@@ -1069,12 +1086,12 @@ hipError_t launch_debug_r(const Crystal &c, const int *quads, int n, const int *
 
 }  // namespace
 
-hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *inv_omega, double2 *E64, float2 *E32,
+hipError_t launch_tables(const Crystal &c, double4 *qbound, double4 *mode4, double *speed, double *inv_omega, double2 *E64, float2 *E32,
                          const double *evec, const double *mass, int4 *qn, double2 *PHA64, double2 *PHB64,
                          double2 *PHD64, float2 *PHD32, const int *avec, const int *bvec,
                          const int *dvec, hipStream_t s) {
   const int nthr = 128;
-  hipLaunchKernelGGL(k_tables, dim3((c.N + nthr - 1) / nthr), dim3(nthr), 0, s, c, qbound, mode4, inv_omega, E64, E32,
+  hipLaunchKernelGGL(k_tables, dim3((c.N + nthr - 1) / nthr), dim3(nthr), 0, s, c, qbound, mode4, speed, inv_omega, E64, E32,
                      evec, mass, qn, PHA64, PHB64, PHD64, PHD32, avec, bvec, dvec);
   return hipGetLastError();
 }
