@@ -133,11 +133,23 @@ def surrogate_main(args):
         c.load_fc3(fc3.atoms, fc3.cells, fc3.phi)
         return inst, c
 
+    ckpt = args.ckpt_dir
+    model_prefix = os.path.join(ckpt, "surrogate") if ckpt else None
+    if ckpt:
+        os.makedirs(ckpt, exist_ok=True)
+    if model_prefix and os.path.exists(model_prefix + ".npy") and os.path.exists(model_prefix + "_train.json"):
+        # resumed pass: the trained network and its training record come from the checkpoint
+        sur = S.Surrogate.load(model_prefix)
+        with open(model_prefix + "_train.json") as f:
+            training = json.load(f)
+        log(f"loaded the trained surrogate from {model_prefix}")
+    else:
+        sur, training = None, None
     rng = np.random.default_rng(0)
     tr, ca = S.TrainSet(), S.TrainSet()
     t_train_exact = 0.0
     t0 = time.perf_counter()
-    for d in range(args.draws):
+    for d in range(args.draws if sur is None else 0):
         inst, c = load(tg, 1000 + d)
         modes = rng.permutation(inst.nmodes)
         n_tr = int(args.sample_frac * inst.nmodes)
@@ -157,20 +169,29 @@ def surrogate_main(args):
         t_train_exact += te + te2
         c.close()
         log(f"draw {d}: exact modes in {te + te2:.1f} s")
-    sur = S.Surrogate(seed=1)
-    X, y = tr.arrays()
-    t1 = time.perf_counter()
-    loss = sur.fit(X, y, epochs=args.epochs, batch=256, lr=1e-3)
-    t_fit = time.perf_counter() - t1
-    kappa = sur.calibrate(*ca.arrays())
-    log(f"trained on {len(y)} rows in {t_fit:.1f} s, loss {loss[0]:.3f} -> {loss[-1]:.3f}, "
-        f"kappa {kappa:.2f}")
+    if sur is None:
+        sur = S.Surrogate(seed=1)
+        X, y = tr.arrays()
+        t1 = time.perf_counter()
+        loss = sur.fit(X, y, epochs=args.epochs, batch=256, lr=1e-3)
+        t_fit = time.perf_counter() - t1
+        kappa = sur.calibrate(*ca.arrays())
+        log(f"trained on {len(y)} rows in {t_fit:.1f} s, loss {loss[0]:.3f} -> {loss[-1]:.3f}, "
+            f"kappa {kappa:.2f}")
+        training = {"rows": int(len(y)), "exact_seconds": t_train_exact, "fit_seconds": t_fit,
+                    "loss_first": float(loss[0]), "loss_last": float(loss[-1]), "kappa": kappa,
+                    "wall_seconds": time.perf_counter() - t0}
+        if model_prefix:
+            sur.save(model_prefix)
+            with open(model_prefix + "_train.json", "w") as f:
+                json.dump(training, f)
     seed = 1000 if not args.unseen_draw else 2000
     inst, c = load(ig, seed)
     log(f"inference grid {ig} ({inst.nmodes} modes) loaded; the exact fallback and audit follow")
     rates, rep = S.infer(sur, c, inst.omega, T_inf, flag_sigma=args.flag_sigma,
                          audit_frac=0.02, audit_seed=7, chunk=64,
-                         progress=lambda what, done, tot: log(f"{what} exact {done}/{tot}"))
+                         progress=lambda what, done, tot: log(f"{what} exact {done}/{tot}"),
+                         ckpt=ckpt, max_exact_seconds=args.max_exact_seconds)
     c.close()
     rep.pop("audit_modes")
     rep.pop("flagged_modes")
@@ -188,9 +209,7 @@ def surrogate_main(args):
                                + ", T=300,700 K",
                    "flag_sigma": args.flag_sigma, "audit_frac": 0.02, "epochs": args.epochs,
                    "sigma_calibration": "held-out draw" if args.calib_draw else "held-out modes"},
-        "training": {"rows": int(len(y)), "exact_seconds": t_train_exact, "fit_seconds": t_fit,
-                     "loss_first": float(loss[0]), "loss_last": float(loss[-1]), "kappa": kappa,
-                     "wall_seconds": time.perf_counter() - t0},
+        "training": training,
         "report": rep,
     }
     print(json.dumps(out))
@@ -533,6 +552,35 @@ def large_main(args):
     print(json.dumps(large_leg(args.subset)))
 
 
+def mfma_probe_main(args):
+    """Matrix cores against vector units on this GPU (fp4_probe_matrix_rates), and what that
+    means for the branch-block products of the rate kernel (H = E3 F, V = H E4^T, 6x6 complex
+    per block for the 2-atom cell): packed two blocks per 16x16 tile (the only sharing the
+    per-block operands allow), the complex products take 4 real products each, K = 6 padded to
+    the instruction's K.  Useful flops per tile: 2 blocks x 432 complex MACs x 8."""
+    import paper_2104_04895_amd as fp4
+    r = fp4.probe_matrix_rates(0)
+    useful = 2 * 432 * 8.0
+    issued_fp64 = 2 * 4 * 2 * (2 * 16 * 16 * 4)        # H and V, 4 real products, 2 k-steps
+    issued_bf16 = 2 * 4 * 3 * 1 * (2 * 16 * 16 * 32)   # H and V, 4 products, 3-product split
+    util64, util16 = useful / issued_fp64, useful / issued_bf16
+    out = {
+        "metric": "matrix cores vs vector units: measured TFLOP/s and the branch-block product placement",
+        "value": r["fp64_mfma_16x16x4"] / r["fp64_valu_fma"], "unit": "x (FP64 MFMA / FP64 VALU rate)",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+        "measured_tflops": r,
+        "overlap": {
+            "fp64_mixed_over_mean_of_halves": r["fp64_half_mfma_half_valu"] / (0.5 * (r["fp64_mfma_16x16x4"] + r["fp64_valu_fma"])),
+            "bf16_mixed_over_mean_of_halves": r["bf16_half_mfma_half_fp32_valu"] / (0.5 * (r["bf16_mfma_16x16x32"] + r["fp32_valu_fma"]))},
+        "block_product": {
+            "tile_utilisation_fp64_mfma": util64, "tile_utilisation_bf16x3_mfma": util16,
+            "effective_tflops_fp64_mfma": r["fp64_mfma_16x16x4"] * util64,
+            "effective_tflops_bf16x3_mfma": r["bf16_mfma_16x16x32"] * util16,
+            "vector_fp64_tflops": r["fp64_valu_fma"], "vector_fp32_tflops": r["fp32_valu_fma"]},
+    }
+    print(json.dumps(out))
+
+
 def cpu_baseline_leg(inst, dq, gpu_proc_per_s):
     """The oracle, as it stands, on the host cores: 8 target modes stratified by frequency
     (evenly spaced ranks among the active modes) x 32 evenly spaced partner points q' of the
@@ -611,6 +659,8 @@ def main():
                     help="phase spaces P4 / WP4 of the 8x8x8 workload against the rates")
     ap.add_argument("--wedge", action="store_true",
                     help="8x8x8 workload on the irreducible grid points against the full grid")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="measure matrix-core against vector-unit rates (branch-block placement)")
     ap.add_argument("--train-grid", type=int, default=12)
     ap.add_argument("--infer-grid", type=int, default=20)
     ap.add_argument("--draws", type=int, default=8)
@@ -620,12 +670,21 @@ def main():
     ap.add_argument("--unseen-draw", action="store_true")
     ap.add_argument("--calib-draw", action="store_true",
                     help="calibrate sigma on a whole held-out draw instead of held-out modes")
+    ap.add_argument("--ckpt-dir", default=None,
+                    help="surrogate: keep the trained network and every finished exact chunk "
+                         "here, and resume from what is there")
+    ap.add_argument("--max-exact-seconds", type=float, default=None,
+                    help="surrogate: start no new exact chunk after this many seconds of the "
+                         "inference pass (resume later with the same --ckpt-dir)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the rate kernel runs on a single MI355X and "
               f"--gpus {args.gpus} is not supported (multi-GPU sharding is a design note).",
               file=sys.stderr)
         sys.exit(2)
+    if args.mfma_probe:
+        mfma_probe_main(args)
+        return
     if args.surrogate:
         surrogate_main(args)
         return

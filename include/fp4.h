@@ -379,6 +379,15 @@ int fp4_mlp_train(fp4_mlp *m, const float *X, const float *y, int32_t n, int32_t
  * (nullable) receives the device time of the forward pass. */
 int fp4_mlp_predict(fp4_mlp *m, const float *X, int32_t n, int32_t bf16, float *out, double *ms);
 
+/* Hardware probe behind the placement of the branch-block contraction (matrix cores only
+ * where they pay): measured TFLOP/s on device `device_id` of six kernels, written to
+ * tflops[6]: 0 FP64 MFMA 16x16x4, 1 FP64 vector FMA, 2 half of the wavefronts of each
+ * work-group as 0 and half as 1, 3 BF16 MFMA 16x16x32 with FP32 accumulation, 4 FP32 vector
+ * FMA, 5 half as 3 and half as 4.  Mixed kernels close to the mean of their halves mean the
+ * matrix core does not run beside the vector unit.  Allocates and frees 4 MiB of device
+ * memory; takes about 20 ms. */
+int fp4_probe_matrix_rates(int32_t device_id, double *tflops);
+
 /* Human-readable reason of the last error on this context ("" if none). */
 const char *fp4_last_error(const fp4_ctx *ctx);
 

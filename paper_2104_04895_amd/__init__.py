@@ -45,6 +45,7 @@ EXPORTED = [
     "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict", "fp4_load_fc3",
     "fp4_compute_rates3", "fp4_surrogate_features", "fp4_compute_rates4_wedge",
     "fp4_compute_rates4_classes", "fp4_compute_rates4_noalloc", "fp4_compute_kappa_rta",
+    "fp4_probe_matrix_rates",
 ]
 FP4_NFEAT = 18
 
@@ -88,6 +89,7 @@ def lib():
         L.fp4_compute_rates4_wedge.argtypes = [P, P, i32, f64, u32, i32, i32, P, P, P, P]
         L.fp4_compute_rates4_classes.argtypes = [P, P, i32, f64, u32, i32, P, i32, P, P, P, P]
         L.fp4_compute_kappa_rta.argtypes = [P, P, i32, f64, i32, P, P, P, P]
+        L.fp4_probe_matrix_rates.argtypes = [i32, P]
         L.fp4_compute_rates4_async.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
         L.fp4_compute_rates4_noalloc.argtypes = [P, P, i32, f64, u32, i32, P, P, P, P]
         L.fp4_debug_matrix_elements.argtypes = [P, i32, P, i32, P]
@@ -494,3 +496,15 @@ def autotune(ctx: "Context", T, scalebroad=1.0, mask=7, precision=FP4_FP64, nsam
                               int(nsample), ctypes.byref(best), _p(ms), _p(qs), 16, ctypes.byref(n)),
                "fp4_autotune")
     return best.value, {int(qs[i]): float(ms[i]) for i in range(n.value)}
+
+
+def probe_matrix_rates(device: int = 0) -> dict:
+    """Measured TFLOP/s of the matrix cores and vector units (fp4_probe_matrix_rates)."""
+    L = lib()
+    t = np.zeros(6)
+    rc = L.fp4_probe_matrix_rates(int(device), _p(t))
+    if rc != FP4_OK:
+        raise Fp4Error(rc, "fp4_probe_matrix_rates failed")
+    keys = ["fp64_mfma_16x16x4", "fp64_valu_fma", "fp64_half_mfma_half_valu",
+            "bf16_mfma_16x16x32", "fp32_valu_fma", "bf16_half_mfma_half_fp32_valu"]
+    return dict(zip(keys, map(float, t)))

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfp4.so")
 SOURCES = [os.path.join(HERE, "csrc", "fp4_api.cpp"), os.path.join(HERE, "csrc", "fp4_kernels.hip"),
            os.path.join(HERE, "csrc", "fp4_mlp.hip"), os.path.join(HERE, "csrc", "fp4_rates3.hip"),
-           os.path.join(HERE, "csrc", "fp4_features.hip"), os.path.join(HERE, "csrc", "fp4_kappa.hip")]
+           os.path.join(HERE, "csrc", "fp4_features.hip"), os.path.join(HERE, "csrc", "fp4_kappa.hip"),
+           os.path.join(HERE, "csrc", "fp4_probe.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

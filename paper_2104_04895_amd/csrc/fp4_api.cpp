@@ -1477,6 +1477,25 @@ int fp4_compute_kappa_rta(fp4_ctx *ctx, const double *T, int32_t nT, double scal
   }
 }
 
+int fp4_probe_matrix_rates(int32_t device_id, double *tflops) {
+  if (!tflops) return FP4_E_INVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device_id < 0 || device_id >= ndev) {
+    (void)hipGetLastError();
+    return FP4_E_DEVICE;
+  }
+  if (hipSetDevice(device_id) != hipSuccess) return FP4_E_DEVICE;
+  double *out = nullptr;
+  if (hipMalloc(&out, fp4::probe_out_doubles() * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return FP4_E_NOMEM;
+  }
+  for (int i = 0; i < 6; ++i) tflops[i] = 0.0;
+  const hipError_t e = fp4::run_probe(out, tflops, nullptr);
+  (void)hipFree(out);
+  return e == hipSuccess ? FP4_OK : FP4_E_DEVICE;
+}
+
 int fp4_last_stats(const fp4_ctx *ctx, int64_t *processes, int64_t *candidates, int64_t *blocks) {
   if (!ctx) return FP4_E_INVAL;
   if (processes) *processes = ctx->st_processes;

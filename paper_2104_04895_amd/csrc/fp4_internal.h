@@ -167,6 +167,10 @@ hipError_t launch_kappa(const Crystal &c, const double *T, int nT, double hk, co
                         const double *r3, const double *r4, double scale, double kb,
                         double *kappa, long long *skipped, hipStream_t s);
 
+// hardware probe (fp4_probe.hip): TFLOP/s of six timed kernels into tflops[6]
+size_t probe_out_doubles();
+hipError_t run_probe(double *out, double *tflops, hipStream_t s);
+
 // launchers (fp4_features.hip)
 hipError_t launch_fc4_strength(const Crystal &c, const int *targets, int nt, double *g4,
                                hipStream_t s);

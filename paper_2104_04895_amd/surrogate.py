@@ -147,28 +147,61 @@ class Surrogate:
 
 
 def exact_chunked(ctx: Context, T, scalebroad, targets, precision=FP4_FP64, chunk=0,
-                  progress=None, what="exact"):
+                  progress=None, what="exact", ckpt=None, deadline=None):
     """Exact rates of `targets` in calls of at most `chunk` modes (0: one call), reporting
-    each finished call to `progress(what, done, total)`.  Returns (rates [nT][nt], seconds)."""
+    each finished call to `progress(what, done, total)`.
+
+    With `ckpt` (a directory) every finished chunk is written there as
+    `<what>_<first>_<n>.npy` (float64 [nT][n], no pickle) together with its target list, and
+    chunks already present with the same targets are read back instead of recomputed, so an
+    interrupted pass resumes where it stopped.  With `deadline` (a time.perf_counter() value)
+    no new chunk starts after it.
+
+    Returns (rates [nT][nt], seconds spent in the exact kernel, done [nt] bool)."""
+    import os
     targets = np.asarray(targets, dtype=np.int32)
     nT = len(np.atleast_1d(T))
     out = np.zeros((nT, targets.size))
+    done = np.zeros(targets.size, dtype=bool)
     step = targets.size if chunk <= 0 else chunk
-    t0 = time.perf_counter()
+    t_exact = 0.0
     for a in range(0, targets.size, max(step, 1)):
-        r, _, _ = ctx.compute_rates4(T, scalebroad, 7, precision, targets[a:a + step], counts=False)
+        tg = targets[a:a + step]
+        path = os.path.join(ckpt, f"{what}_{a:08d}_{tg.size}.npy") if ckpt else None
+        if path and os.path.exists(path) and os.path.exists(path[:-4] + "_targets.npy"):
+            r = np.load(path, allow_pickle=False)
+            same = np.array_equal(np.load(path[:-4] + "_targets.npy", allow_pickle=False), tg)
+            if same and r.shape == (nT, tg.size):
+                out[:, a:a + step] = r
+                done[a:a + step] = True
+                continue
+        if deadline is not None and time.perf_counter() > deadline:
+            continue
+        t0 = time.perf_counter()
+        r, _, _ = ctx.compute_rates4(T, scalebroad, 7, precision, tg, counts=False)
+        t_exact += time.perf_counter() - t0
         out[:, a:a + step] = r
+        done[a:a + step] = True
+        if path:
+            np.save(path[:-4] + "_targets.npy", tg)
+            np.save(path, r)
         if progress:
             progress(what, min(a + step, targets.size), targets.size)
-    return out, time.perf_counter() - t0
+    return out, t_exact, done
 
 
 def infer(sur: Surrogate, ctx: Context, omega, T, scalebroad=1.0, flag_sigma=0.2,
           audit_frac=0.02, audit_seed=0, precision=FP4_FP64, bf16=True, chunk=0,
-          progress=None):
+          progress=None, ckpt=None, max_exact_seconds=None):
     """Rates of every mode of the context's grid: surrogate predictions, with flagged modes
     and a random audit sample of the others recomputed by the exact kernel (in calls of at
     most `chunk` modes, each reported to `progress`).
+
+    `ckpt` (a directory) keeps every finished exact chunk, so a pass cut short resumes
+    where it stopped (see exact_chunked); `max_exact_seconds` stops starting new exact chunks
+    after that much wall time, and the report's "complete" is then False.  An audited mode
+    whose exact rate is zero (no kept process) while the prediction is positive counts as a
+    miss: it is reported apart ("audit_zero_rate") and in the within-10% fraction.
 
     Returns (rates [nT][nq*nb], report dict)."""
     T = np.atleast_1d(np.asarray(T, np.float64))
@@ -201,30 +234,39 @@ def infer(sur: Surrogate, ctx: Context, omega, T, scalebroad=1.0, flag_sigma=0.2
     rates[:, active] = np.exp(mu)
     pred_audit = np.exp(mu[:, audit])
 
+    deadline = None if max_exact_seconds is None else time.perf_counter() + max_exact_seconds
     t_audit = t_flag = 0.0
+    done_a = np.ones(0, bool)
     if audit.size:
-        ra, t_audit = exact_chunked(ctx, T, scalebroad, active[audit], precision, chunk,
-                                    progress, "audit")
-        rates[:, active[audit]] = ra
+        ra, t_audit, done_a = exact_chunked(ctx, T, scalebroad, active[audit], precision, chunk,
+                                            progress, "audit", ckpt, deadline)
+        rates[:, active[audit]] = np.where(done_a[None, :], ra, rates[:, active[audit]])
     else:
         ra = np.zeros((nT, 0))
     fl = np.flatnonzero(flagged)
+    done_f = np.ones(0, bool)
     if fl.size:
-        rf, t_flag = exact_chunked(ctx, T, scalebroad, active[fl], precision, chunk, progress,
-                                   "flagged")
-        rates[:, active[fl]] = rf
+        rf, t_flag, done_f = exact_chunked(ctx, T, scalebroad, active[fl], precision, chunk,
+                                           progress, "flagged", ckpt, deadline)
+        rates[:, active[fl]] = np.where(done_f[None, :], rf, rates[:, active[fl]])
+    rep["complete"] = bool(done_a.all() and done_f.all())
+    rep["exact_done"] = {"audit": int(done_a.sum()), "flagged": int(done_f.sum())}
 
     # audit statistics: relative error of the predictions that were kept for every other mode
-    if audit.size:
-        good = ra > 0
-        rel = np.abs(pred_audit[good] - ra[good]) / ra[good]
-        z = np.abs(mu[:, audit][good] - np.log(ra[good])) / sig[:, audit][good]
+    if audit.size and done_a.any():
+        ra_d, pa_d = ra[:, done_a], pred_audit[:, done_a]
+        good = ra_d > 0
+        rel = np.abs(pa_d[good] - ra_d[good]) / ra_d[good]
+        z = np.abs(mu[:, audit][:, done_a][good] - np.log(ra_d[good])) / sig[:, audit][:, done_a][good]
+        nzero = int((~good).sum())
         rep["audit_rel_err"] = {
             "median": float(np.median(rel)), "p90": float(np.quantile(rel, 0.9)),
             "p99": float(np.quantile(rel, 0.99)), "max": float(rel.max()),
-            "mean": float(rel.mean()), "frac_within_10pct": float(np.mean(rel <= 0.1)),
+            "mean": float(rel.mean()),
+            "frac_within_10pct": float(np.sum(rel <= 0.1) / (rel.size + nzero)),
             "frac_within_2sigma": float(np.mean(z <= 2.0)), "n": int(rel.size)}
-    per_target = t_audit / max(audit.size, 1)
+        rep["audit_zero_rate"] = nzero
+    per_target = t_audit / max(int(done_a.sum()), 1)
     t_total = t_feat + t_pred + t_audit + t_flag
     rep.update({
         "flagged": int(fl.size), "flagged_frac": float(fl.size / max(active.size, 1)),

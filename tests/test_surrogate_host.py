@@ -73,7 +73,34 @@ def test_infer_flags_audit_and_replacement():
 def test_exact_chunked_reports_progress():
     ctx = FakeCtx(100)
     seen = []
-    r, _ = S.exact_chunked(ctx, [300.0], 1.0, np.arange(37), chunk=10,
-                           progress=lambda w, d, t: seen.append((d, t)))
+    r, _, done = S.exact_chunked(ctx, [300.0], 1.0, np.arange(37), chunk=10,
+                                 progress=lambda w, d, t: seen.append((d, t)))
     assert seen == [(10, 37), (20, 37), (30, 37), (37, 37)]
+    assert done.all()
     np.testing.assert_allclose(r[0], np.arange(37) + 1.0)
+
+
+def test_exact_chunked_resumes_from_checkpoint(tmp_path):
+    """A pass stopped by its deadline after the first chunk leaves that chunk on disk; the
+    second pass reads it back and computes only the rest, with the same result."""
+    import time
+    ctx = FakeCtx(100)
+    r1, _, done1 = S.exact_chunked(ctx, [300.0], 1.0, np.arange(37), chunk=10, what="flagged",
+                                   ckpt=str(tmp_path), deadline=time.perf_counter() - 1.0)
+    assert not done1.any() and sum(ctx.calls) == 0          # past the deadline: nothing starts
+    calls = []
+    ctx2 = FakeCtx(100)
+    ctx2.calls = calls
+    S.exact_chunked(ctx2, [300.0], 1.0, np.arange(37)[:10], chunk=10, what="flagged",
+                    ckpt=str(tmp_path))                          # writes chunk 0 (targets 0..9)
+    assert calls == [10]
+    ctx3 = FakeCtx(100)
+    r3, _, done3 = S.exact_chunked(ctx3, [300.0], 1.0, np.arange(37), chunk=10, what="flagged",
+                                   ckpt=str(tmp_path))
+    assert done3.all() and ctx3.calls == [10, 10, 7]          # chunk 0 read back
+    np.testing.assert_allclose(r3[0], np.arange(37) + 1.0)
+    # a chunk file whose target list differs is recomputed, not trusted
+    ctx4 = FakeCtx(100)
+    S.exact_chunked(ctx4, [300.0], 1.0, np.arange(1, 38), chunk=10, what="flagged",
+                    ckpt=str(tmp_path))
+    assert ctx4.calls == [10, 10, 10, 7]
