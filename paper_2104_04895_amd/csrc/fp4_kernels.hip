@@ -436,14 +436,14 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
 // accumulated into the lane's FP64 partial rates.  Entry i of L is (s << 6) | b for source
 // lane s = (group g, row r) and code b: b < NB is the process (lambda'' = (q''_g, r),
 // lambda''' = (q'''_g, b)), NB <= b < 2 NB the mirrored one (lambda'' = (q'''_g, b - NB),
-// lambda''' = (q''_g, r)), b >= 2 NB both of column b - 2 NB (redistribution channel, both
-// kept).  The two members of a mirror pair share |V| (V transposed), |v'' - v'''| and so
+// lambda''' = (q''_g, r)), b >= 2 NB both of column b - 2 NB (redistribution or splitting
+// channel, both kept).  The two members of a mirror pair share |V| (V transposed), |v'' - v'''| and so
 // sigma, 1/(w'' w''') and the occupation factor; one evaluation serves both, each with its
 // own dw formed in its stand-alone order and its own Gaussian.  V is read from the group's
 // tile, (q''_g, q'''_g) from Gq (bit 30 of q'''_g: the block's processes are Umklapp ones).
 // Consecutive lanes take consecutive entries, so every lane has work while the list lasts.
 // With a.qclass == 3 the sums go by class instead of by channel: normal processes to
-// acc.r[0], Umklapp ones to acc.r[1] (adding 0.0 elsewhere leaves the other sums exact).
+// acc.r[0], Umklapp ones to acc.r[1].
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const unsigned short *L, int cnt, int lane,
@@ -475,7 +475,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
     const ModeRec<NT> p2 = load_rec<NB, NT>(c, a, mu2), p3 = load_rec<NB, NT>(c, a, mu3);
     double dw, s2, dwm = 0.0;
     window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
-    if (CH == 1 && pair) {
+    if (CH != 0 && pair) {
       // the mirrored member (lambda'' and lambda''' exchanged); its s2 equals s2 exactly
       double s2m;
       window_keep(add_signed(aw, p3.m.w, S2), p2.m.w, p3.m, p2.m, a.c_win, dwm, s2m);
@@ -486,7 +486,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
     }
     const double sig2 = a.c_sig * s2;
-    double delta = (CH == 1 && pair) ? 2.0 : 1.0;
+    double delta = (CH != 0 && pair) ? 2.0 : 1.0;
     if (!(sig2 < a.c_min)) {
       // adaptive Gaussian exp(-dw^2/sigma^2) / (sqrt(pi) sigma), 1/sqrt(pi) =
       // 0.5641895835477563; y = 1/sigma from the hardware reciprocal square root refined
@@ -497,7 +497,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       const double y2 = y * y, x0 = (dw * dw) * y2;
       const double e0 = exp(-x0);
       delta = e0 * (0.5641895835477563 * y);
-      if (CH == 1 && pair) {
+      if (CH != 0 && pair) {
         // the mirrored member's exponent differs from x0 only by the rounding of its dw
         // (|x0 - x1| <= 1e-8 for any sigma above the floor), so exp(-x1) =
         // e0 exp(d) = e0 (1 + d + d^2/2) to far below the FP64 rounding, d = x0 - x1
@@ -526,7 +526,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
         }
       }
     }
-    acc.cnt[CH] += (CH == 1 && pair) ? 2 : 1;
+    acc.cnt[CH] += (CH != 0 && pair) ? 2 : 1;
   }
 }
 
@@ -558,8 +558,11 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   constexpr int S1 = (CH == 2) ? -1 : 1;
   constexpr int S2 = (CH == 0) ? 1 : -1;
   constexpr bool MIRROR = (CH == 1);
-  // mirror pairs share one contraction only for a slot-3/slot-4 symmetric quartet list
-  const bool mir = MIRROR && a.mirror != 0;
+  // In the redistribution and splitting channels slots 3 and 4 are both conjugated, so for a
+  // slot-3/slot-4 symmetric quartet list the blocks q'' and q''' are transposes: one
+  // contraction serves the mirror pair.  Redistribution queues one block of every pair in
+  // grid order; splitting scans the sorted list and queues the pair from its lower index.
+  const bool mir = CH != 0 && a.mirror != 0;
   constexpr double WCH = (CH == 2) ? (1.0 / 6.0) : 0.5;
   constexpr unsigned long long GMASK = (1ull << NB) - 1ull;
   const CR *Ws = W + (S1 > 0 ? 0 : c.ng * 9);
@@ -569,15 +572,22 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   const double kw = a.harmonic == 2 ? WCH * a.kpref : WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
   const unsigned long long lt = (1ull << lane) - 1ull;
   const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
+  // queue entries hold q'' and q''' packed (15 bits each) on grids of up to 2^15 points, so
+  // the contraction phase does not recompute the fold; larger grids queue q'' alone
+  const bool pack = c.N <= 32768;
   // ++ and --: q'' is scanned in ascending order of its lowest active frequency, and only as
   // far as a row can pass the window.  A kept process has |dw| <= sqrt(c_win) |v'' - v'''|
   // <= 2 sqrt(c_win) v_hi, with dw = aw + w'' - w''' (++) or aw - w'' - w''' (--), so its row
   // frequency w'' is at most thr = w_hi - aw + win (++) or aw - w_lo + win (--).  The margins
   // are far above the FP64 rounding of the exact test, so no kept process is skipped.
+  // In the splitting channel the same bound holds for w''' (the two slots enter dw alike), so
+  // a block whose q''' has its lowest frequency above thr holds no kept process, and a
+  // mirror pair has both members in the scanned part of the list or no kept process.
   int nscan = c.N;
+  double thr = 0.0;
   if (!MIRROR) {
     const double win = 2.0 * a.sqrt_c_win * c.v_hi * (1.0 + 1e-6) + 1e-9 * (fabs(aw) + c.w_hi) + 1e-12;
-    const double thr = (S2 > 0 ? c.w_hi - aw : aw - c.w_lo) + win;
+    thr = (S2 > 0 ? c.w_hi - aw : aw - c.w_lo) + win;
     // count the sorted entries <= thr: whole 64ths of the list first, then the boundary one
     const int seg = (c.N + 63) >> 6;
     const bool le = lane * seg < c.N && c.qord_w[min(c.N, (lane + 1) * seg) - 1] <= thr;
@@ -624,7 +634,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         d2.z += DK.z + cy;
         const bool lead = glane && iq2c < c.N && (!mir || iq2c <= iq3c) && r == 0;
         const unsigned long long lb = __ballot(lead);
-        if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
+        if (lead) Qw[cnt + __popcll(lb & lt)] = pack ? (iq2c | (iq3c << 15)) : iq2c;
         cnt += __popcll(lb);
       }
     } else {
@@ -645,7 +655,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       double2 *cs = reinterpret_cast<double2 *>(Xg);
       for (int k = k0; k < k1; ++k) {
         const bool livec = live;
-        const int iq2c = iq2;
+        const int iq2c = iq2, iq3c = iq3;
         const double4 vrc = vr, qbc = qb;
         const double spc = sp;
         // lane r holds column record r of the round; the group shares the six through its tile
@@ -666,16 +676,19 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         }
         wave_sync();
         bool keep = false;
-        if (livec) {
+        // splitting with mirror pairs: the pair {q'', q'''} is taken from its lower index,
+        // with both orientations tested; a q''' outside the scanned part holds no kept process
+        const bool lead_pair = !mir || (iq2c <= iq3c && qbc.x <= thr);
+        if (livec && lead_pair) {
           unsigned b0, b1;
-          row_bits_cols<NB, S2>(a, aw, vrc, spc, qbc, cs, false, b0, b1);
-          const unsigned long long bal = __ballot(b0 != 0u);
+          row_bits_cols<NB, S2>(a, aw, vrc, spc, qbc, cs, mir && iq2c != iq3c, b0, b1);
+          const unsigned long long bal = __ballot((b0 | b1) != 0u);
           keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
         }
         wave_sync();
         const bool lead = keep && r == 0;
         const unsigned long long lb = __ballot(lead);
-        if (lead) Qw[cnt + __popcll(lb & lt)] = iq2c;
+        if (lead) Qw[cnt + __popcll(lb & lt)] = pack ? (iq2c | (iq3c << 15)) : iq2c;
         cnt += __popcll(lb);
       }
     }
@@ -688,15 +701,21 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       int iq2 = 0, iq3 = 0;
       unsigned bA = 0u, bB = 0u;
       if (act) {
-        iq2 = Qw[e];
-        // grid digits of q'' by division (no index-table load on the critical path)
-        int4 n2;
-        {
-          int t;
-          divmod_small(iq2, c.g0, inv_g0, t, n2.x);
-          divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
+        const int qv = Qw[e];
+        if (pack) {
+          iq2 = qv & 0x7fff;
+          iq3 = qv >> 15;
+        } else {
+          iq2 = qv;
+          // grid digits of q'' by division (no index-table load on the critical path)
+          int4 n2;
+          {
+            int t;
+            divmod_small(iq2, c.g0, inv_g0, t, n2.x);
+            divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
+          }
+          iq3 = fold_d(n2);
         }
-        iq3 = fold_d(n2);
         // lane r reads column record r; the group shares the six through its tile
         const double4 vc = c.mode4[iq3 * NB + r];
         double2 *cs = reinterpret_cast<double2 *>(Xg);
