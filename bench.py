@@ -15,8 +15,9 @@ fallback rate and the speedup over the plain FP64 kernel.
 
 ``--batched`` runs the uneven-instance workload: a 2-atom cubic 10x10x10 grid, a 4-atom
 wurtzite-like 8x8x6 grid and a 4-atom layered 6x6x6 grid at T = 300, 700 K in one
-persistent graph-captured launch with the FP32 contraction and autotuned q' chunks, timed
-against separate calls, with every rate compared to the FP64 path.
+persistent graph-captured launch with the FP32 contraction and autotuned work shapes (q'
+chunk, queue and list segments), timed against separate calls, with every rate compared to
+the FP64 path.
 
 ``--batched-small`` runs 28 small instances (24 diamond-structure cells on 2x2x2 .. 4x4x4
 grids and 4 three-atom cells) in one graph replay against one synchronous call each.
@@ -232,10 +233,11 @@ def batched_main(args):
         c = fp4.Context(0)
         c.load_instance(inst)
         c.set_param(fp4.FP4_PARAM_PROFILE, 1)
-        best, table = fp4.autotune(c, T, 1.0, 7, fp4.FP4_FP32, nsample=32)
-        tuned.append({"instance": inst.name, "qchunk": best, "ms_by_qchunk": table})
+        best, table = fp4.autotune_shapes(c, T, 1.0, 7, fp4.FP4_FP32, nsample=32)
+        tuned.append({"instance": inst.name, "qchunk_qseg_lseg": list(best),
+                      "ms_by_config": [[list(cfg), ms] for cfg, ms in table]})
         ctxs.append(c)
-        log(f"{inst.name}: {inst.nmodes} modes, autotuned q' chunk {best}")
+        log(f"{inst.name}: {inst.nmodes} modes, autotuned (q' chunk, queue, list) {best}")
     ref, t64, t32, procs = [], [], [], []
     for inst, c in zip(insts, ctxs):
         t0 = time.perf_counter()

@@ -64,6 +64,10 @@ extern "C" {
                                      sum_d (n_d/N_d + m_d) b_d over m_d in -2..1, ties (relative
                                      1e-10) to the first m in the order m1, m2, m3.  Rates and
                                      counts of compute calls are then those of the class. */
+#define FP4_PARAM_QSEG 7          /* q'' points a wavefront queues for contraction per phase
+                                     of the rate kernel (multiple of 64, 64..2048; default 256) */
+#define FP4_PARAM_LSEG 8          /* kept processes a wavefront evaluates per pass of the rate
+                                     kernel (multiple of 64, 64..4096; default 256) */
 #define FP4_PARAM_PHASE_SPACE 6   /* 0 rates (default); otherwise compute calls return a
                                      four-phonon phase space in place of the rates, with no
                                      force constants used (|V|^2 := 1, no contraction):
@@ -346,6 +350,17 @@ const char *fp4_batch_last_error(const fp4_batch *b);
 int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, uint32_t mask,
                  int32_t precision, int32_t nsample, int32_t *best_qchunk, double *ms_out,
                  int32_t *qchunk_out, int32_t ncand_max, int32_t *ncand);
+
+/* Autotuner of the rate kernel's work shapes: first the q'-chunk as fp4_autotune, then at
+ * that chunk the queue segment FP4_PARAM_QSEG and the list segment FP4_PARAM_LSEG over
+ * {128, 256, 512} x {128, 256, 512} (configurations whose LDS exceeds a work-group's 160 KiB
+ * are skipped), each timed on the persistent pipeline over `nsample` evenly spaced active
+ * modes.  The fastest (qchunk, qseg, lseg) becomes the context's setting and is returned in
+ * best[3]; cand_out [ncand_max][3] and ms_out [ncand_max] (nullable) receive the tried
+ * configurations and their device times, *ncand their number.  1 <= nT <= 4. */
+int fp4_autotune_shapes(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                        uint32_t mask, int32_t precision, int32_t nsample, int32_t *best,
+                        double *ms_out, int32_t *cand_out, int32_t ncand_max, int32_t *ncand);
 
 /* ---------------------------------------------------------------- learned surrogate
  * A small multilayer perceptron, trained and evaluated by the library's own kernels, that

@@ -31,6 +31,8 @@ FP4_PARAM_QCHUNK = 3
 FP4_PARAM_PROFILE = 4
 FP4_PARAM_QCLASS = 5
 FP4_PARAM_PHASE_SPACE = 6
+FP4_PARAM_QSEG = 7
+FP4_PARAM_LSEG = 8
 
 FP4_PP, FP4_PM, FP4_MM = 1, 2, 4
 
@@ -45,7 +47,7 @@ EXPORTED = [
     "fp4_mlp_loss_grad", "fp4_mlp_train", "fp4_mlp_predict", "fp4_load_fc3",
     "fp4_compute_rates3", "fp4_surrogate_features", "fp4_compute_rates4_wedge",
     "fp4_compute_rates4_classes", "fp4_compute_rates4_noalloc", "fp4_compute_kappa_rta",
-    "fp4_probe_matrix_rates",
+    "fp4_probe_matrix_rates", "fp4_autotune_shapes",
 ]
 FP4_NFEAT = 18
 
@@ -108,6 +110,7 @@ def lib():
         L.fp4_batch_last_error.argtypes = [P]
         L.fp4_batch_last_error.restype = ctypes.c_char_p
         L.fp4_autotune.argtypes = [P, P, i32, f64, u32, i32, i32, P, P, P, i32, P]
+        L.fp4_autotune_shapes.argtypes = [P, P, i32, f64, u32, i32, i32, P, P, P, i32, P]
         u64 = ctypes.c_uint64
         L.fp4_mlp_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, i32, i32, i32, u64]
         L.fp4_mlp_destroy.argtypes = [P]
@@ -496,6 +499,22 @@ def autotune(ctx: "Context", T, scalebroad=1.0, mask=7, precision=FP4_FP64, nsam
                               int(nsample), ctypes.byref(best), _p(ms), _p(qs), 16, ctypes.byref(n)),
                "fp4_autotune")
     return best.value, {int(qs[i]): float(ms[i]) for i in range(n.value)}
+
+
+def autotune_shapes(ctx: "Context", T, scalebroad=1.0, mask=7, precision=FP4_FP64, nsample=64):
+    """Run the work-shape autotuner (q'-chunk, then queue and list segments); returns
+    ((qchunk, qseg, lseg), [((qchunk, qseg, lseg), ms), ...])."""
+    L = lib()
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+    best = np.zeros(3, dtype=np.int32)
+    ms = np.zeros(32)
+    cand = np.zeros((32, 3), dtype=np.int32)
+    n = ctypes.c_int32()
+    ctx._check(L.fp4_autotune_shapes(ctx._h, _p(T), len(T), float(scalebroad), int(mask),
+                                     int(precision), int(nsample), _p(best), _p(ms), _p(cand), 32,
+                                     ctypes.byref(n)), "fp4_autotune_shapes")
+    return tuple(int(x) for x in best), [(tuple(int(x) for x in cand[i]), float(ms[i]))
+                                         for i in range(min(n.value, 32))]
 
 
 def probe_matrix_rates(device: int = 0) -> dict:

@@ -78,6 +78,7 @@ struct fp4_ctx {
   // parameters
   double window_w = 2.0, sigma_min = 1e-4;
   int qchunk = 0, profile = 0;
+  int qseg = 256, lseg = 256;   // queue and list segments of the rate kernel (autotuned)
 
   // regrouped quartet list (host)
   int ng = 0, nc = 0, nq4 = 0, na = 0, nbv = 0, nd = 0;
@@ -379,6 +380,8 @@ int enqueue(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t mask, int
   a.occ = (const double *)ctx->d_occ.p;
   a.inv_occ = (const double *)ctx->d_iocc.p;
   a.qchunk = qchunk;
+  a.qseg = ctx->qseg;
+  a.lseg = ctx->lseg;
   a.nchunk = nchunk;
   a.nxcd = kXcds;
   a.U = ctx->d_U.p;
@@ -838,6 +841,16 @@ int fp4_set_param(fp4_ctx *ctx, int32_t key, double value) {
         return ctx->fail(FP4_E_INVAL, "phase-space kind must be 0 (rates), 1 (WP4) or 2 (P4)");
       ctx->harmonic = (int)value;
       return FP4_OK;
+    case FP4_PARAM_QSEG:
+      if (!(value >= 64.0 && value <= 2048.0) || std::fmod(value, 64.0) != 0.0)
+        return ctx->fail(FP4_E_INVAL, "queue segment must be a multiple of 64 in [64, 2048]");
+      ctx->qseg = (int)value;
+      return FP4_OK;
+    case FP4_PARAM_LSEG:
+      if (!(value >= 64.0 && value <= 4096.0) || std::fmod(value, 64.0) != 0.0)
+        return ctx->fail(FP4_E_INVAL, "list segment must be a multiple of 64 in [64, 4096]");
+      ctx->lseg = (int)value;
+      return FP4_OK;
     case FP4_PARAM_QCLASS:
       if (!(value == 0.0 || value == 1.0 || value == 2.0))
         return ctx->fail(FP4_E_INVAL, "process class must be 0 (all), 1 (normal) or 2 (Umklapp)");
@@ -1101,6 +1114,8 @@ int fp4_compute_rates4_noalloc(fp4_ctx *ctx, const double *T, int32_t nT, double
   a.inv_occ = iocc;
   a.targets = nullptr;
   a.qchunk = qchunk;
+  a.qseg = ctx->qseg;
+  a.lseg = ctx->lseg;
   a.nchunk = nchunk;
   a.nxcd = kXcds;
   a.U = U;
@@ -1579,6 +1594,8 @@ int prepare_instance(fp4_ctx *ctx, const double *T, int nT, double sb, uint32_t 
   a.nt = nt;
   a.t0 = 0;
   a.qchunk = qchunk;
+  a.qseg = ctx->qseg;
+  a.lseg = ctx->lseg;
   a.nchunk = nchunk;
   a.nxcd = kXcds;
   a.U = ctx->d_U.p;
@@ -1620,7 +1637,7 @@ int enqueue_batch(fp4_batch *b, std::vector<fp4::BatchInst> (&cls)[4], int fp32,
     size_t lds = 0;
     for (auto &bi : cls[k]) {
       total = std::max(total, bi.item0 + (long long)bi.a.nt * bi.a.nchunk);
-      lds = std::max(lds, fp4::batch_lds_bytes(bi.c, fp32, nT));
+      lds = std::max(lds, fp4::batch_lds_bytes(bi.c, fp32, nT, bi.a.qseg, bi.a.lseg));
     }
     hipError_t e = fp4::launch_batch((const fp4::BatchInst *)b->d_inst[k].p, (int)cls[k].size(), total,
                                      (unsigned long long *)b->d_counter.p + (size_t)k * fp4::kClassCounters, lds, fp32,
@@ -1814,6 +1831,53 @@ int fp4_batch_last_timing(const fp4_batch *b, double *ms_graph, int64_t *graph_b
   return FP4_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device time (ms) of the persistent rate pipeline on the sample targets with the given
+// q'-chunk, queue segment and list segment (one untimed pass first).
+int time_config(fp4_ctx *ctx, fp4_batch *b, const std::vector<int> &sample, const double *T,
+                int nT, double sb, uint32_t mask, int precision, int qchunk, int qseg, int lseg,
+                bool warm, float *ms) {
+  const int keep_qs = ctx->qseg, keep_ls = ctx->lseg;
+  ctx->qseg = qseg;
+  ctx->lseg = lseg;
+  std::vector<fp4::BatchInst> insts;
+  std::vector<fp4::BatchInst> cls[4];
+  std::vector<fp4_ctx *> one{ctx};
+  int rc = build_classes(b, one, {sample}, T, nT, sb, mask, precision, {qchunk}, insts, cls);
+  if (!rc && warm) rc = enqueue_batch(b, cls, precision == FP4_FP32, nT, one, insts, b->stream);
+  if (!rc && hipEventRecord(b->ev0, b->stream) != hipSuccess) rc = FP4_E_DEVICE;
+  if (!rc) rc = enqueue_batch(b, cls, precision == FP4_FP32, nT, one, insts, b->stream);
+  if (!rc && (hipEventRecord(b->ev1, b->stream) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess))
+    rc = FP4_E_DEVICE;
+  *ms = 0.f;
+  if (!rc) (void)hipEventElapsedTime(ms, b->ev0, b->ev1);
+  ctx->qseg = keep_qs;
+  ctx->lseg = keep_ls;
+  return rc;
+}
+
+// Evenly spaced active modes of the context (the autotuner's sample).
+int tune_sample(fp4_ctx *ctx, int nsample, std::vector<int> &sample) {
+  const int nm = ctx->N * ctx->nb;
+  std::vector<double> om(nm);
+  FP4_HIP(ctx, hipMemcpy(om.data(), ctx->d_omega.p, nm * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<int> act;
+  for (int m = 0; m < nm; ++m)
+    if (om[m] > 0.0) act.push_back(m);
+  if (act.empty()) return ctx->fail(FP4_E_STATE, "no active mode");
+  const int ns = std::min<int>(nsample, (int)act.size());
+  sample.clear();
+  for (int i = 0; i < ns; ++i) sample.push_back(act[(size_t)i * act.size() / ns]);
+  return FP4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, uint32_t mask,
                  int32_t precision, int32_t nsample, int32_t *best_qchunk, double *ms_out,
                  int32_t *qchunk_out, int32_t ncand_max, int32_t *ncand) {
@@ -1824,17 +1888,8 @@ int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, u
     if (nT > 4) return ctx->fail(FP4_E_UNSUPPORTED, "autotuning takes at most 4 temperatures");
     if (nsample < 1) return ctx->fail(FP4_E_INVAL, "nsample must be >= 1");
     (void)hipSetDevice(ctx->device);
-    // sample: evenly spaced active modes
-    const int nm = ctx->N * ctx->nb;
-    std::vector<double> om(nm);
-    FP4_HIP(ctx, hipMemcpy(om.data(), ctx->d_omega.p, nm * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<int> act;
-    for (int m = 0; m < nm; ++m)
-      if (om[m] > 0.0) act.push_back(m);
-    if (act.empty()) return ctx->fail(FP4_E_STATE, "no active mode");
     std::vector<int> sample;
-    const int ns = std::min<int>(nsample, (int)act.size());
-    for (int i = 0; i < ns; ++i) sample.push_back(act[(size_t)i * act.size() / ns]);
+    if ((rc = tune_sample(ctx, nsample, sample))) return rc;
     std::vector<int> cand;
     for (int q : {1, 2, 4, 8, 16, 32, 64, 128})
       if (q < ctx->N) cand.push_back(q);
@@ -1844,34 +1899,19 @@ int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, u
     double best_ms = 1e300;
     int best = cand[0];
     std::vector<double> times;
-    for (size_t ci = 0; ci <= cand.size(); ++ci) {
-      // the first pass (ci == 0, repeated) warms caches and code; it is not counted
-      const int q = cand[ci == 0 ? 0 : ci - 1];
-      std::vector<fp4::BatchInst> insts;
-      std::vector<fp4::BatchInst> cls[4];
-      std::vector<fp4_ctx *> one{ctx};
-      rc = build_classes(b, one, {sample}, T, nT, scalebroad, mask, precision, {q}, insts, cls);
-      if (!rc) {
-        rc = enqueue_batch(b, cls, precision == FP4_FP32, nT, one, insts, b->stream);
-        if (!rc && hipEventRecord(b->ev0, b->stream) != hipSuccess) rc = FP4_E_DEVICE;
-      }
-      // time only the persistent part: re-enqueue after the first event
-      if (!rc) {
-        rc = enqueue_batch(b, cls, precision == FP4_FP32, nT, one, insts, b->stream);
-        if (!rc && (hipEventRecord(b->ev1, b->stream) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)) rc = FP4_E_DEVICE;
-      }
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+      float ms = 0.f;
+      rc = time_config(ctx, b, sample, T, nT, scalebroad, mask, precision, cand[ci], ctx->qseg,
+                       ctx->lseg, ci == 0, &ms);
       if (rc) {
         const std::string msg = b->err;
         fp4_batch_destroy(b);
         return ctx->fail(rc, "autotune: " + msg);
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
-      if (ci == 0) continue;
       times.push_back(ms);
       if (ms < best_ms) {
         best_ms = ms;
-        best = q;
+        best = cand[ci];
       }
     }
     fp4_batch_destroy(b);
@@ -1881,6 +1921,85 @@ int fp4_autotune(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad, u
     for (int i = 0; i < (int)times.size() && i < ncand_max; ++i) {
       if (ms_out) ms_out[i] = times[i];
       if (qchunk_out) qchunk_out[i] = cand[i];
+    }
+    ctx->err.clear();
+    return FP4_OK;
+  } catch (const std::bad_alloc &) {
+    return ctx->fail(FP4_E_NOMEM, "host allocation failed");
+  }
+}
+
+int fp4_autotune_shapes(fp4_ctx *ctx, const double *T, int32_t nT, double scalebroad,
+                        uint32_t mask, int32_t precision, int32_t nsample, int32_t *best,
+                        double *ms_out, int32_t *cand_out, int32_t ncand_max, int32_t *ncand) {
+  if (!ctx) return FP4_E_INVAL;
+  try {
+    int rc = check_compute_args(ctx, T, nT, scalebroad, mask, precision);
+    if (rc) return rc;
+    if (nT > 4) return ctx->fail(FP4_E_UNSUPPORTED, "autotuning takes at most 4 temperatures");
+    if (nsample < 1) return ctx->fail(FP4_E_INVAL, "nsample must be >= 1");
+    (void)hipSetDevice(ctx->device);
+    std::vector<int> sample;
+    if ((rc = tune_sample(ctx, nsample, sample))) return rc;
+    struct Cfg {
+      int qchunk, qseg, lseg;
+      double ms;
+    };
+    std::vector<Cfg> tried;
+    fp4_batch *b = nullptr;
+    if ((rc = fp4_batch_create(&b, ctx->device))) return ctx->fail(rc, "batch context creation failed");
+    auto run = [&](int qc, int qs, int ls, bool warm, double *ms_res) {
+      float ms = 0.f;
+      const int r = time_config(ctx, b, sample, T, nT, scalebroad, mask, precision, qc, qs, ls, warm, &ms);
+      if (!r) {
+        tried.push_back(Cfg{qc, qs, ls, (double)ms});
+        *ms_res = ms;
+      }
+      return r;
+    };
+    // stage 1: q'-chunk at the current segments; stage 2: queue and list segments at the
+    // best chunk (configurations whose LDS does not fit a work-group are skipped)
+    std::vector<int> qcs;
+    for (int q : {1, 2, 4, 8, 16, 32, 64, 128})
+      if (q < ctx->N) qcs.push_back(q);
+    qcs.push_back(ctx->N);
+    Cfg bestc{qcs[0], ctx->qseg, ctx->lseg, 1e300};
+    for (size_t i = 0; i < qcs.size() && !rc; ++i) {
+      double ms = 0.0;
+      rc = run(qcs[i], ctx->qseg, ctx->lseg, i == 0, &ms);
+      if (!rc && ms < bestc.ms) bestc = Cfg{qcs[i], ctx->qseg, ctx->lseg, ms};
+    }
+    const fp4::Crystal c = make_crystal(ctx);
+    for (int qs : {128, 256, 512})
+      for (int ls : {128, 256, 512}) {
+        if (rc || (qs == bestc.qseg && ls == bestc.lseg)) continue;
+        if (fp4::batch_lds_bytes(c, precision == FP4_FP32, nT, qs, ls) > 160 * 1024 - 64) continue;
+        double ms = 0.0;
+        rc = run(bestc.qchunk, qs, ls, false, &ms);
+        if (!rc && ms < bestc.ms) bestc = Cfg{bestc.qchunk, qs, ls, ms};
+      }
+    if (rc) {
+      const std::string msg = b->err;
+      fp4_batch_destroy(b);
+      return ctx->fail(rc, "autotune: " + msg);
+    }
+    fp4_batch_destroy(b);
+    ctx->qchunk = bestc.qchunk;
+    ctx->qseg = bestc.qseg;
+    ctx->lseg = bestc.lseg;
+    if (best) {
+      best[0] = bestc.qchunk;
+      best[1] = bestc.qseg;
+      best[2] = bestc.lseg;
+    }
+    if (ncand) *ncand = (int)tried.size();
+    for (int i = 0; i < (int)tried.size() && i < ncand_max; ++i) {
+      if (ms_out) ms_out[i] = tried[i].ms;
+      if (cand_out) {
+        cand_out[3 * i] = tried[i].qchunk;
+        cand_out[3 * i + 1] = tried[i].qseg;
+        cand_out[3 * i + 2] = tried[i].lseg;
+      }
     }
     ctx->err.clear();
     return FP4_OK;

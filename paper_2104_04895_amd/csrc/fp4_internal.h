@@ -72,6 +72,8 @@ struct RateArgs {
   int nt;                   // targets in this batch
   int t0;                   // index of the first target of the batch in the output
   int qchunk;               // q' points per work-group
+  int qseg;                 // q'' points a wavefront queues per phase (multiple of 64)
+  int lseg;                 // kept processes a wavefront evaluates per pass (>= 64)
   int nchunk;               // ceil(N / qchunk)
   int nxcd;                 // XCDs the work-groups are dealt to (blockIdx round-robin)
   const void *U;            // [nt][nc][27] complex (R) precontraction of the batch
@@ -135,7 +137,7 @@ hipError_t launch_occupations_v(const Crystal &c, const double *T, int nT, doubl
 // off .. off + nt - 1, counts [stride][3] at rows off ..
 hipError_t launch_reduce_strided(const RateArgs &a, int nt, int stride, int off, double *rates,
                                  double *rates_ch, long long *counts, hipStream_t s);
-size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT);
+size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT, int qseg, int lseg);
 
 // Allocation-free scratch area: a file-scope device array of kScratchBytes per GPU.
 // scratch_init() looks up its address on the current device (once per device) and returns
@@ -149,7 +151,7 @@ hipError_t launch_reduce(const RateArgs &a, int nt_total, double *rates, double 
 hipError_t launch_debug_v(const Crystal &c, const int *quads, int n, const int *tslot,
                           const void *U, int fp32, double2 *V, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
-size_t batch_lds_bytes(const Crystal &c, int fp32, int nT);
+size_t batch_lds_bytes(const Crystal &c, int fp32, int nT, int qseg, int lseg);
 hipError_t launch_batch(const BatchInst *insts, int ninst, long long total,
                         unsigned long long *counter, size_t lds, int fp32, int nb, int nT,
                         int *grid_out, hipStream_t s);

@@ -530,8 +530,8 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
   }
 }
 
-constexpr int QSEG = 256;   // q'' points a wavefront queues at a time
-constexpr int LSEG = 256;   // kept processes a wavefront evaluates per pass
+// Per wavefront, a.qseg q'' points are queued at a time and a.lseg kept processes evaluated
+// per pass (both set by the host; the autotuner picks them with the q'-chunk).
 
 // All blocks (q'') of one channel for fixed lambda, lambda'.  Each wavefront owns a quarter
 // of the q'' points.  Phase 1 compacts the blocks worth contracting into the wavefront's LDS
@@ -602,7 +602,8 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   // q'' (or the sorted list) is dealt to the wavefronts in rounds of GPW consecutive points, so that every
   // wavefront sees the whole range (the mirror-pair members are not spread evenly over it)
   const int nk = (nscan + 4 * GPW - 1) / (4 * GPW);
-  constexpr int KSEG = QSEG / GPW;
+  const int KSEG = a.qseg / GPW;
+  const int LSEG = a.lseg;
   // the column point is fold(b3 + s'' q''), b3 = q + s' q'; DK = grid digits of the
   // per-round step 4 GPW of q''
   const int4 b3 = make_int4(nq.x + S1 * nq1.x, nq.y + S1 * nq1.y, nq.z + S1 * nq1.z, 0);
@@ -612,6 +613,21 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
     const int y = wrap(b3.y + S2 * n2.y, c.g1);
     const int z = wrap(b3.z + S2 * n2.z, c.g2);
     return x + c.g0 * (y + c.g1 * z);
+  };
+  // a queue entry back to (q'', q'''): unpacked, or q''' folded from the grid digits of q''
+  // found by division (no index-table load on the critical path)
+  auto unpack_q = [&](int qv, int &iq2, int &iq3) {
+    if (pack) {
+      iq2 = qv & 0x7fff;
+      iq3 = qv >> 15;
+    } else {
+      iq2 = qv;
+      int4 n2;
+      int t;
+      divmod_small(iq2, c.g0, inv_g0, t, n2.x);
+      divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
+      iq3 = fold_d(n2);
+    }
   };
   for (int k0 = 0; k0 < nk; k0 += KSEG) {
     const int k1 = min(nk, k0 + KSEG);
@@ -638,22 +654,57 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         cnt += __popcll(lb);
       }
     } else {
-      // the first nscan points of the sorted list, the blocks with a surviving process; the
-      // list entry two rounds ahead and the row and bound records of the next round are
-      // fetched while the current round is tested
-      constexpr int STEP = 4 * GPW;
-      int p = (k0 * 4 + wave) * GPW + gw;
-      const int4 s0 = c.qord[min(p, c.N - 1)];
-      int4 sn = c.qord[min(p + STEP, c.N - 1)];
-      int iq2 = s0.x, iq3 = fold_d(make_int4(s0.y, s0.z, s0.w, 0));
-      bool live = glane && p < nscan;
+      // stage A: every lane tests one point of the segment's part of the sorted list against
+      // a bound on its whole block: dw of any process of (q'', q''') lies in
+      // [aw + w''_min - w'''_max, aw + w''_max - w'''_min] (++) or
+      // [aw - w''_max - w'''_max, aw - w''_min - w'''_min] (--), and a kept one has
+      // |dw| <= sqrt(c_win) (v''_max + v'''_max); the interval is widened by 1e-9 of the
+      // frequencies entering it (far above its FP64 rounding) and the bound by 1e-6, so no
+      // block with a kept process is dropped.  In the splitting channel the interval is the
+      // same for both orientations of a mirror pair.  The survivors are compacted into Qw.
+      const double bmar = 1e-9 * (fabs(aw) + 2.0 * c.w_hi) + 1e-12;
+      const int npt = (k1 - k0) * GPW;
+      int ns = 0;
+      for (int i0 = 0; i0 < npt; i0 += 64) {
+        const int i = i0 + lane;
+        const int kr = i / GPW;
+        const int p = ((k0 + kr) * 4 + wave) * GPW + (i - kr * GPW);
+        bool sv = false;
+        int iq2 = 0, iq3 = 0;
+        if (i < npt && p < nscan) {
+          const int4 s = c.qord[p];
+          iq2 = s.x;
+          iq3 = fold_d(make_int4(s.y, s.z, s.w, 0));
+          const double4 b2 = c.qbound[iq2], b3 = c.qbound[iq3];
+          const double lo = S2 > 0 ? (aw + b2.x) - b3.y : (aw - b2.y) - b3.y;
+          const double hi = S2 > 0 ? (aw + b2.y) - b3.x : (aw - b2.x) - b3.x;
+          const double lim = a.sqrt_c_win * (b2.z + b3.z) * (1.0 + 1e-6) + bmar;
+          sv = !(lo > lim) && !(hi < -lim);
+          // splitting with mirror pairs: the pair {q'', q'''} is taken from its lower index,
+          // with both orientations tested; a q''' outside the scanned part holds no kept
+          // process
+          if (mir) sv = sv && iq2 <= iq3 && b3.x <= thr;
+        }
+        const unsigned long long bal = __ballot(sv);
+        if (sv) Qw[ns + __popcll(bal & lt)] = pack ? (iq2 | (iq3 << 15)) : iq2;
+        ns += __popcll(bal);
+      }
+      wave_sync();
+      // stage B: the lane groups take the surviving points GPW at a time and test their rows
+      // against the six columns (the next round's records are fetched while the current one
+      // is tested); the blocks with a kept process are queued in place, below the entries
+      // still to be read
+      int e = gw;
+      bool live = glane && e < ns;
+      int iq2 = 0, iq3 = 0;
+      if (live) unpack_q(Qw[e], iq2, iq3);
       const double4 z4 = make_double4(0.0, 0.0, 0.0, 0.0);
       double4 vr = live ? c.mode4[iq2 * NB + r] : z4;
       double sp = live ? c.speed[iq2 * NB + r] : 0.0;
       double4 qb = live ? c.qbound[iq3] : z4;
       double4 vc = live ? c.mode4[iq3 * NB + r] : z4;
       double2 *cs = reinterpret_cast<double2 *>(Xg);
-      for (int k = k0; k < k1; ++k) {
+      for (int j0 = 0; j0 < ns; j0 += GPW) {
         const bool livec = live;
         const int iq2c = iq2, iq3c = iq3;
         const double4 vrc = vr, qbc = qb;
@@ -663,12 +714,10 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
           cs[2 * r] = make_double2(vc.x, vc.y);
           cs[2 * r + 1] = make_double2(vc.z, vc.w);
         }
-        p += STEP;
-        iq2 = sn.x;
-        iq3 = fold_d(make_int4(sn.y, sn.z, sn.w, 0));
-        sn = c.qord[min(p + STEP, c.N - 1)];
-        live = glane && k + 1 < k1 && p < nscan;
+        e += GPW;
+        live = glane && e < ns;
         if (live) {
+          unpack_q(Qw[e], iq2, iq3);
           vr = c.mode4[iq2 * NB + r];
           sp = c.speed[iq2 * NB + r];
           qb = c.qbound[iq3];
@@ -676,10 +725,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         }
         wave_sync();
         bool keep = false;
-        // splitting with mirror pairs: the pair {q'', q'''} is taken from its lower index,
-        // with both orientations tested; a q''' outside the scanned part holds no kept process
-        const bool lead_pair = !mir || (iq2c <= iq3c && qbc.x <= thr);
-        if (livec && lead_pair) {
+        if (livec) {
           unsigned b0, b1;
           row_bits_cols<NB, S2>(a, aw, vrc, spc, qbc, cs, mir && iq2c != iq3c, b0, b1);
           const unsigned long long bal = __ballot((b0 | b1) != 0u);
@@ -701,21 +747,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       int iq2 = 0, iq3 = 0;
       unsigned bA = 0u, bB = 0u;
       if (act) {
-        const int qv = Qw[e];
-        if (pack) {
-          iq2 = qv & 0x7fff;
-          iq3 = qv >> 15;
-        } else {
-          iq2 = qv;
-          // grid digits of q'' by division (no index-table load on the critical path)
-          int4 n2;
-          {
-            int t;
-            divmod_small(iq2, c.g0, inv_g0, t, n2.x);
-            divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
-          }
-          iq3 = fold_d(n2);
-        }
+        unpack_q(Qw[e], iq2, iq3);
         // lane r reads column record r; the group shares the six through its tile
         const double4 vc = c.mode4[iq3 * NB + r];
         double2 *cs = reinterpret_cast<double2 *>(Xg);
@@ -799,8 +831,8 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
   int2 *Gq = reinterpret_cast<int2 *>(P + NGRP * c.nd); // [NGRP] current block of each group
   int *sg_d = reinterpret_cast<int *>(Gq + NGRP);       // [ng]
   int *skl = sg_d + c.ng;                               // [nat*nat + 1]
-  int *Q = skl + c.nat * c.nat + 1;                     // [4][QSEG] block queues
-  unsigned short *L = reinterpret_cast<unsigned short *>(Q + 4 * QSEG);  // [4][LSEG]
+  int *Q = skl + c.nat * c.nat + 1;                     // [4][qseg] block queues
+  unsigned short *L = reinterpret_cast<unsigned short *>(Q + 4 * a.qseg);  // [4][lseg]
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int gw = lane / NB, r = lane - gw * NB;
@@ -808,10 +840,10 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
   const int G = wave * GPW + gw;
   CR *Xg = X + (size_t)(glane ? G : 0) * XT;
   CR *Pg = P + (size_t)(glane ? G : 0) * c.nd;
-  int *Qw = Q + wave * QSEG;
+  int *Qw = Q + wave * a.qseg;
   const CR *Xw = X + (size_t)wave * GPW * XT;
   int2 *Gqw = Gq + wave * GPW;
-  unsigned short *Lw = L + wave * LSEG;
+  unsigned short *Lw = L + wave * a.lseg;
   for (int i = tid; i < c.ng; i += 256) sg_d[i] = c.g_d[i];
   for (int i = tid; i <= c.nat * c.nat; i += 256) skl[i] = c.kl_start[i];
 
@@ -1041,20 +1073,20 @@ __global__ void k_zero(unsigned long long *p, size_t n) {
   if (i < n) p[i] = 0ull;
 }
 
-size_t rate_lds_bytes(const Crystal &c, int fp32, int NT) {
+size_t rate_lds_bytes(const Crystal &c, int fp32, int NT, int qseg, int lseg) {
   const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
   const int NB = c.nb, GPW = 64 / NB;
   const size_t lds = cb * ((size_t)2 * c.ng * 9 + (size_t)4 * GPW * xtile(NB, (int)cb) + (size_t)4 * GPW * c.nd) +
                      sizeof(int2) * (size_t)4 * GPW +
-                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1 + 4 * QSEG) +
-                     sizeof(unsigned short) * (size_t)4 * LSEG;
+                     sizeof(int) * ((size_t)c.ng + c.nat * c.nat + 1 + (size_t)4 * qseg) +
+                     sizeof(unsigned short) * (size_t)4 * lseg;
   const size_t lds_red = sizeof(double) * 4 * 3 * NT + sizeof(unsigned long long) * 16;
   return lds > lds_red ? lds : lds_red;
 }
 
 template <typename R, int NB, int NT>
 hipError_t launch_rates_t(const Crystal &c, const RateArgs &a, hipStream_t s) {
-  const size_t bytes = rate_lds_bytes(c, sizeof(R) == 4, NT);
+  const size_t bytes = rate_lds_bytes(c, sizeof(R) == 4, NT, a.qseg, a.lseg);
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((size_t)a.nt * a.nchunk);
   hipLaunchKernelGGL((k_rates<R, NB, NT>), dim3(grid), dim3(256), bytes, s, c, a);
@@ -1148,8 +1180,8 @@ hipError_t launch_occupations_v(const Crystal &c, const double *T, int nT, doubl
   return hipGetLastError();
 }
 
-size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT) {
-  return rate_lds_bytes(c, fp32, nT <= 1 ? 1 : nT <= 2 ? 2 : nT <= 4 ? 4 : 8);
+size_t rate_lds_bytes_for(const Crystal &c, int fp32, int nT, int qseg, int lseg) {
+  return rate_lds_bytes(c, fp32, nT <= 1 ? 1 : nT <= 2 ? 2 : nT <= 4 ? 4 : 8, qseg, lseg);
 }
 
 namespace {
@@ -1183,8 +1215,8 @@ hipError_t launch_rates(const Crystal &c, const RateArgs &a, int fp32, hipStream
   return fp32 ? launch_rates_r<float>(c, a, s) : launch_rates_r<double>(c, a, s);
 }
 
-size_t batch_lds_bytes(const Crystal &c, int fp32, int nT) {
-  return rate_lds_bytes(c, fp32, nT <= 1 ? 1 : nT <= 2 ? 2 : 4) + 64;
+size_t batch_lds_bytes(const Crystal &c, int fp32, int nT, int qseg, int lseg) {
+  return rate_lds_bytes(c, fp32, nT <= 1 ? 1 : nT <= 2 ? 2 : 4, qseg, lseg) + 64;
 }
 
 template <typename R, int NB, int NT>

@@ -111,3 +111,31 @@ def test_autotune(fp4, instances):
         r, _, cnt = c.compute_rates4([300.0], 1.0, 7, fp4.FP4_FP64)
     assert np.array_equal(cnt, cref)
     assert _rel(r, ref) <= 1e-13
+
+
+def test_autotune_shapes(fp4, instances):
+    """The work-shape autotuner tries the q'-chunks, then queue and list segments at the best
+    chunk, keeps the fastest configuration in the context; any setting of the segments (here
+    also the smallest, 64 and 64, which forces many phases and passes) gives the same counts
+    and rates equal to rounding, and the oracle's rates within 1e-10."""
+    _say("case: autotune shapes")
+    inst = instances[0]
+    m = oracle.Model.from_instance(inst)
+    r_o, _, c_o = oracle.rates4(m, [300.0, 700.0], 1.0, 7, oracle.default_dq(inst.cr.A, inst.grid))
+    with _ctx(fp4, inst) as c:
+        best, tried = fp4.autotune_shapes(c, [300.0, 700.0], 1.0, 7, fp4.FP4_FP64, nsample=24)
+        cfgs = [cfg for cfg, _ in tried]
+        assert best in cfgs and len(cfgs) >= 4
+        assert dict(tried)[best] == min(ms for _, ms in tried)
+        assert len({(q, l) for _, q, l in cfgs}) >= 2
+        r, _, cnt = c.compute_rates4([300.0, 700.0], 1.0, 7, fp4.FP4_FP64)
+        c.set_param(fp4.FP4_PARAM_QSEG, 64)
+        c.set_param(fp4.FP4_PARAM_LSEG, 64)
+        r64, _, cnt64 = c.compute_rates4([300.0, 700.0], 1.0, 7, fp4.FP4_FP64)
+        r32, _, cnt32 = c.compute_rates4([300.0, 700.0], 1.0, 7, fp4.FP4_FP32)
+        with pytest.raises(fp4.Fp4Error):
+            c.set_param(fp4.FP4_PARAM_QSEG, 100)
+    assert np.array_equal(cnt, c_o) and np.array_equal(cnt64, c_o) and np.array_equal(cnt32, c_o)
+    assert _rel(r, r_o) <= 1e-10 and _rel(r64, r_o) <= 1e-10
+    assert _rel(r64, r) <= 1e-12
+    assert _rel(r32, r_o) <= 1e-4

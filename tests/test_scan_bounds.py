@@ -1,8 +1,9 @@
 """The frequency bounds the rate kernel uses to skip work never drop a kept process.
 
 The kernel scans q'' of the ++ and -- channels in ascending order of the lowest active
-frequency at q'' and stops at a threshold, and culls a row (q'', j'') from the frequency
-range and largest speed at q'''.  Both rest on the same inequality: a kept process has
+frequency at q'' and stops at a threshold, culls a block (q'', q''') from the frequency
+ranges and largest speeds at both points, and a row (q'', j'') from the frequency range and
+largest speed at q'''.  Both rest on the same inequality: a kept process has
 |dw| <= sqrt(c_win) |v'' - v'''| (the window of the adaptive Gaussian, Sec. 2.4 / App. B),
 hence |dw| <= sqrt(c_win) (|v''| + v_max(q''')) <= 2 sqrt(c_win) v_max.  Here every candidate
 process of the 3x3x3 workload is tested with the exact FP64 predicate (same operation order
@@ -81,5 +82,15 @@ def test_kept_processes_respect_the_scan_and_cull_bounds(sb):
                 dist = np.maximum(np.maximum(x - wmax_q[q3k], wmin_q[q3k] - x), 0.0)
                 lim = sq * (sp2 + vmax_q[q3k])
                 assert np.all(dist <= lim * (1 + 1e-12) + 1e-12)
+                # block cull: distance of 0 from the dw range of the block (q'', q''')
+                if s2 > 0:
+                    lo = awk + wmin_q[q2k] - wmax_q[q3k]
+                    hi = awk + wmax_q[q2k] - wmin_q[q3k]
+                else:
+                    lo = awk - wmax_q[q2k] - wmax_q[q3k]
+                    hi = awk - wmin_q[q2k] - wmin_q[q3k]
+                bdist = np.maximum(np.maximum(lo, -hi), 0.0)
+                blim = sq * (vmax_q[q2k] + vmax_q[q3k])
+                assert np.all(bdist <= blim * (1 + 1e-12) + 1e-12)
     # the bounds were exercised on kept processes of both channels
     assert kept_total[0] > 0 and kept_total[2] > 0
