@@ -152,12 +152,13 @@ def exact_chunked(ctx: Context, T, scalebroad, targets, precision=FP4_FP64, chun
     each finished call to `progress(what, done, total)`.
 
     With `ckpt` (a directory) every finished chunk is written there as
-    `<what>_<first>_<n>.npy` (float64 [nT][n], no pickle) together with its target list, and
-    chunks already present with the same targets are read back instead of recomputed, so an
-    interrupted pass resumes where it stopped.  With `deadline` (a time.perf_counter() value)
-    no new chunk starts after it.
+    `<what>_<first>_<n>.npy` (float64 [nT][n], no pickle) together with its target list and
+    the seconds its exact call took, and chunks already present with the same targets are
+    read back instead of recomputed, so an interrupted pass resumes where it stopped.  With
+    `deadline` (a time.perf_counter() value) no new chunk starts after it.
 
-    Returns (rates [nT][nt], seconds spent in the exact kernel, done [nt] bool)."""
+    Returns (rates [nT][nt], seconds spent in the exact kernel, done [nt] bool); the seconds
+    include those recorded with chunks read back (a chunk without a record counts zero)."""
     import os
     targets = np.asarray(targets, dtype=np.int32)
     nT = len(np.atleast_1d(T))
@@ -174,16 +175,21 @@ def exact_chunked(ctx: Context, T, scalebroad, targets, precision=FP4_FP64, chun
             if same and r.shape == (nT, tg.size):
                 out[:, a:a + step] = r
                 done[a:a + step] = True
+                sec = path[:-4] + "_seconds.npy"
+                if os.path.exists(sec):
+                    t_exact += float(np.load(sec, allow_pickle=False).reshape(-1)[0])
                 continue
         if deadline is not None and time.perf_counter() > deadline:
             continue
         t0 = time.perf_counter()
         r, _, _ = ctx.compute_rates4(T, scalebroad, 7, precision, tg, counts=False)
-        t_exact += time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        t_exact += dt
         out[:, a:a + step] = r
         done[a:a + step] = True
         if path:
             np.save(path[:-4] + "_targets.npy", tg)
+            np.save(path[:-4] + "_seconds.npy", np.array([dt]))
             np.save(path, r)
         if progress:
             progress(what, min(a + step, targets.size), targets.size)

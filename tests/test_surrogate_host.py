@@ -2,6 +2,7 @@
 flagging, the audit sample, replacement by exact rates, the error report and the chunked
 exact calls.  (The network, the features and the exact kernel are tested on the GPU.)"""
 import numpy as np
+import pytest
 
 from paper_2104_04895_amd import FP4_NFEAT
 from paper_2104_04895_amd import surrogate as S
@@ -95,10 +96,18 @@ def test_exact_chunked_resumes_from_checkpoint(tmp_path):
                     ckpt=str(tmp_path))                          # writes chunk 0 (targets 0..9)
     assert calls == [10]
     ctx3 = FakeCtx(100)
-    r3, _, done3 = S.exact_chunked(ctx3, [300.0], 1.0, np.arange(37), chunk=10, what="flagged",
-                                   ckpt=str(tmp_path))
+    r3, t3, done3 = S.exact_chunked(ctx3, [300.0], 1.0, np.arange(37), chunk=10, what="flagged",
+                                    ckpt=str(tmp_path))
     assert done3.all() and ctx3.calls == [10, 10, 7]          # chunk 0 read back
     np.testing.assert_allclose(r3[0], np.arange(37) + 1.0)
+    # the seconds of every chunk are on disk, and a pass that reads them all back reports
+    # their sum as its exact time
+    secs = sum(float(np.load(tmp_path / f"flagged_{a:08d}_{n}_seconds.npy")[0])
+               for a, n in ((0, 10), (10, 10), (20, 10), (30, 7)))
+    ctx5 = FakeCtx(100)
+    _, t5, done5 = S.exact_chunked(ctx5, [300.0], 1.0, np.arange(37), chunk=10, what="flagged",
+                                   ckpt=str(tmp_path))
+    assert done5.all() and ctx5.calls == [] and t5 == pytest.approx(secs) and t5 >= t3
     # a chunk file whose target list differs is recomputed, not trusted
     ctx4 = FakeCtx(100)
     S.exact_chunked(ctx4, [300.0], 1.0, np.arange(1, 38), chunk=10, what="flagged",
