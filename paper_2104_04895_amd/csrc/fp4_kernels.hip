@@ -257,13 +257,19 @@ __device__ void build_W(const Crystal &c, const typename CT<R>::T *Ut, int iq1, 
 
 // ------------------------------------------------------------------ branch block
 
+// With the FP64 contraction the rate kernel leaves H = E3 F in the group tile and forms
+// V[r][cc] = H[r][:] . conj(E4[cc][:]) only for the kept entries, in the Gamma list (a
+// third of the 36 per block); with the FP32 contraction the dense V = H E4^T measured
+// faster.
+template <typename R> constexpr bool VLIST = sizeof(R) == 8;
+
 // Row r (= j'') of V[j''][j'''] for the block (lambda, lambda', q'', channel with sign S2):
 //   F[(k,gamma)][(l,theta)] = sum_{d of (k,l)} exp(i s'' q''.d) W[(k,l,d)][gamma theta]
 //   V = E3 F E4^T,  E3[j''][(k,gamma)] = (E[q''][j''][3k+gamma])^(s''),
 //                   E4[j'''][(l,theta)] = conj(E[q'''][j'''][3l+theta])
 // The nb lanes of a group hold one row each and exchange F rows and E4 rows through the
 // group's LDS tile Xg[nb][nb] (all lanes of a group belong to one wavefront).
-template <typename R, int NB, int S2>
+template <typename R, int NB, int S2, bool HONLY = false>
 __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>::T *Ws,
                                           int iq2, int iq3, int r,
                                           typename CT<R>::T *Xg, typename CT<R>::T *Pg,
@@ -320,7 +326,7 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
   // the row of E4 (lane r: conj(E[q'''][r][:])) is fetched before H = E3[r][:] F when the
   // registers allow it (FP32)
   const CR *e4 = Etab<R>(c) + ((size_t)iq3 * NB + r) * NB;
-  constexpr bool PRE4 = sizeof(R) == 4;
+  constexpr bool PRE4 = sizeof(R) == 4 && !HONLY;
   CR e4v[NB];
   if (PRE4) {
 #pragma unroll
@@ -339,6 +345,13 @@ __device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>
     for (int col = 0; col < NB; ++col) pin(H[col]);
   }
   wave_sync();
+  if constexpr (HONLY) {
+    // the rate kernel forms V[r][cc] = H[r][:] . conj(E4[cc][:]) only for the kept
+    // entries, in the Gamma list: lane r leaves its row of H in the tile
+#pragma unroll
+    for (int col = 0; col < NB; ++col) Xg[r * NB + col] = H[col];
+    return;
+  }
 #pragma unroll
   for (int col = 0; col < NB; ++col) Xg[r * NB + col] = cconj(PRE4 ? e4v[col] : e4[col]);
   wave_sync();
@@ -439,9 +452,10 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
 // lambda''' = (q''_g, r)), b >= 2 NB both of column b - 2 NB (redistribution or splitting
 // channel, both kept).  The two members of a mirror pair share |V| (V transposed), |v'' - v'''| and so
 // sigma, 1/(w'' w''') and the occupation factor; one evaluation serves both, each with its
-// own dw formed in its stand-alone order and its own Gaussian.  V is read from the group's
-// tile, (q''_g, q'''_g) from Gq (bit 30 of q'''_g: the block's processes are Umklapp ones).
-// Consecutive lanes take consecutive entries, so every lane has work while the list lasts.
+// own dw formed in its stand-alone order and its own Gaussian.  V comes from the group's
+// tile (dense V, or H and a row of E4, see VLIST), (q''_g, q'''_g) from Gq (bit 30 of
+// q'''_g: the block's processes are Umklapp ones).  Consecutive lanes take consecutive
+// entries, so every lane has work while the list lasts.
 // With a.qclass == 3 the sums go by class instead of by channel: normal processes to
 // acc.r[0], Umklapp ones to acc.r[1].
 template <typename R, int NB, int NT, int CH>
@@ -452,7 +466,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
   constexpr int S2 = (CH == 0) ? 1 : -1;
-  auto decode = [&](int i, int &mu2, int &mu3, int &vi, bool &pair, bool &umk) {
+  auto decode = [&](int i, int &mu2, int &mu3, int &vi, int &cc, int &m4, bool &pair, bool &umk) {
     const unsigned d = L[i];
     const int s = (int)(d >> 6), b = (int)(d & 63u);
     const int g = s / NB, r = s - g * NB;
@@ -460,17 +474,18 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
     umk = (q.y >> 30) != 0;
     const bool mir = b >= NB && b < 2 * NB;
     pair = b >= 2 * NB;
-    const int cc = pair ? b - 2 * NB : (mir ? b - NB : b);
+    cc = pair ? b - 2 * NB : (mir ? b - NB : b);
     const int mr = q.x * NB + r, mc = (q.y & 0x3fffffff) * NB + cc;
     mu2 = mir ? mc : mr;
     mu3 = mir ? mr : mc;
-    vi = g * xtile(NB, sizeof(CR)) + r * NB + cc;
+    vi = g * xtile(NB, sizeof(CR)) + r * NB;
+    m4 = mc;
   };
 #pragma unroll 1
   for (int i = lane; i < cnt; i += 64) {
-    int mu2, mu3, vi;
+    int mu2, mu3, vi, cc, m4;
     bool pair, umk;
-    decode(i, mu2, mu3, vi, pair, umk);
+    decode(i, mu2, mu3, vi, cc, m4, pair, umk);
     const bool split = a.qclass == 3;
     const ModeRec<NT> p2 = load_rec<NB, NT>(c, a, mu2), p3 = load_rec<NB, NT>(c, a, mu3);
     double dw, s2, dwm = 0.0;
@@ -482,7 +497,17 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
     }
     double v2abs = 1.0;
     if (a.harmonic == 0) {
-      const CR vv = Xw[vi];
+      CR vv;
+      if constexpr (VLIST<R>) {
+        // V[r][cc] = H[r][:] . conj(E4[cc][:]) (the same products in the same order as the
+        // dense V = H E4^T), H from the group's tile, the row of E4 (q''', cc) from the table
+        const CR *e4 = Etab<R>(c) + (size_t)m4 * NB;
+        vv = czero<CR>();
+#pragma unroll
+        for (int col = 0; col < NB; ++col) cmac(vv, Xw[vi + col], cconj(e4[col]));
+      } else {
+        vv = Xw[vi + cc];
+      }
       v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
     }
     const double sig2 = a.c_sig * s2;
@@ -776,9 +801,11 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       if (blk && r == 0) acc.blocks += 1;
       if (blk && a.harmonic == 0) {   // the phase spaces take |V|^2 := 1
         CR V[NB];
-        block_row<R, NB, S2>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
+        block_row<R, NB, S2, VLIST<R>>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
+        if constexpr (!VLIST<R>) {
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
+          for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
+        }
       }
       if (act && r == 0) Gq[gw] = make_int2(iq2, iq3 | (umk ? (1 << 30) : 0));
       // the lane's list entries: single orientations, then mirror pairs with both kept
