@@ -52,13 +52,14 @@ PEAK_FP32_VALU = 157.3e12
 
 # Counter readings of one FP64 k_rates launch on this workload, from the rocprofv3 summary
 # named in "source" (FETCH_SIZE and WRITE_SIZE scaled by their readings for a plain kernel
-# that reads and writes 256 MiB; SQ_INSTS_VALU and the FP64 FMA + MUL + ADD counters).  They
-# are reported only while kernel_build_key() equals "build_key": the kernel sources without
-# comments, the hipcc flags and the ROCm release they were taken with.  The chip issues at
-# most one wave64 FP64 VALU instruction per CU per cycle: 256 CUs x 2.4 GHz.
-COUNTERS_FP64 = {"build_key": None, "source": "profiles/k_rates_diamond8x8x8_fp64.md",
-                 "traffic_bytes": None, "valu_insts": None, "fp64_insts": None,
-                 "mfma_insts": None}
+# that reads and writes 256 MiB; SQ_INSTS_VALU, the FP64 FMA + MUL + ADD counters and
+# SQ_INSTS_MFMA).  They are reported only while kernel_build_key() equals "build_key": the
+# kernel sources without comments, the hipcc flags and the ROCm release they were taken
+# with.  The chip issues at most one wave64 FP64 VALU instruction per CU per cycle: 256 CUs
+# x 2.4 GHz.
+COUNTERS_FP64 = {"build_key": "2ad8f94c36cf5504", "source": "profiles/k_rates_diamond8x8x8_fp64.md",
+                 "traffic_bytes": 1448412706.0, "valu_insts": 411275660638.0,
+                 "fp64_insts": 194202759596.0, "mfma_insts": 0.0}
 VALU_ISSUE_PER_S = 256 * 2.4e9
 
 
