@@ -555,6 +555,55 @@ def large_main(args):
     print(json.dumps(large_leg(args.subset)))
 
 
+def large_full_main(args):
+    """16x16x16 grid (24 576 modes), second-shell FC4, T = 300 K, scalebroad 1: every active
+    mode, in FP64 and with the FP32 contraction, in calls of `chunk` target modes (each call
+    logged, so a long run shows progress); the rates of the two paths are compared mode by
+    mode.  Time = sum of the calls' main-kernel times (HIP events) and their wall time."""
+    import synth
+    import paper_2104_04895_amd as fp4
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    inst = synth.large()
+    ctx = fp4.Context(0)
+    ctx.load_instance(inst)
+    ctx.set_param(fp4.FP4_PARAM_PROFILE, 1)
+    act = np.flatnonzero(inst.omega.reshape(-1) > 0).astype(np.int32)
+    chunk = args.full_chunk
+    out, rates = {}, {}
+    for name, prec in (("fp64", fp4.FP4_FP64), ("fp32", fp4.FP4_FP32)):
+        ms, wall, procs = 0.0, 0.0, 0
+        r_all = np.zeros((len(inst.T), act.size))
+        for a in range(0, act.size, chunk):
+            tg = act[a:a + chunk]
+            t0 = time.perf_counter()
+            r, _, cnt = ctx.compute_rates4(inst.T, 1.0, 7, prec, tg)
+            wall += time.perf_counter() - t0
+            ms += ctx.last_timing()["ms_main"]
+            procs += int(cnt.sum())
+            r_all[:, a:a + chunk] = r
+            log(f"{name}: {min(a + chunk, act.size)}/{act.size} modes, kernel {ms / 1e3:.1f} s")
+        rates[name] = r_all
+        out[name] = {"kernel_s": ms / 1e3, "wall_s": wall, "processes": procs,
+                     "processes_per_s": procs / (ms / 1e3)}
+    r64, r32 = rates["fp64"], rates["fp32"]
+    rel = np.abs(r32 - r64) / np.maximum(np.abs(r64), 1e-300)
+    rel[r64 == 0] = 0.0
+    out["fp32"]["max_rel_err_vs_fp64_path"] = float(rel.max())
+    out["fp32"]["median_rel_err_vs_fp64_path"] = float(np.median(rel[r64 > 0]))
+    ctx.close()
+    print(json.dumps({
+        "metric": "4ph processes/sec and rates time-to-solution; FP64 vs mixed at stated rel. err",
+        "value": out["fp64"]["processes_per_s"], "unit": "processes/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"diamond-structure 2-atom cell, 16x16x16 grid (24576 modes), "
+                               f"second-shell FC4, T=300 K, sb 1, every active mode "
+                               f"({act.size}) in calls of {chunk}"},
+        "paths": out, "fp32_speedup": out["fp64"]["kernel_s"] / out["fp32"]["kernel_s"]}))
+
+
 def mfma_probe_main(args):
     """Matrix cores against vector units on this GPU (fp4_probe_matrix_rates), and what that
     means for the branch-block products of the rate kernel (H = E3 F, V = H E4^T, 6x6 complex
@@ -652,6 +701,9 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="16x16x16 workload on a random subset of target modes, FP64 and FP32")
     ap.add_argument("--subset", type=int, default=512)
+    ap.add_argument("--large-full", action="store_true",
+                    help="every mode of the 16x16x16 grid, FP64 and FP32 (about 11 minutes)")
+    ap.add_argument("--full-chunk", type=int, default=2048)
     ap.add_argument("--batched", action="store_true",
                     help="run the batched uneven-instance workload (one graph-captured launch)")
     ap.add_argument("--batched-small", action="store_true",
@@ -705,6 +757,9 @@ def main():
         return
     if args.phase_space:
         phase_space_main(args)
+        return
+    if args.large_full:
+        large_full_main(args)
         return
     if args.large:
         large_main(args)
