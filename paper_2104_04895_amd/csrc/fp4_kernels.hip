@@ -640,11 +640,17 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
   // per-round step 4 GPW of q''
   const int4 b3 = make_int4(nq.x + S1 * nq1.x, nq.y + S1 * nq1.y, nq.z + S1 * nq1.z, 0);
   const int4 DK = make_int4((4 * GPW) % c.g0, ((4 * GPW) / c.g0) % c.g1, (4 * GPW) / (c.g0 * c.g1), 0);
-  auto fold_d = [&](int4 n2) {
-    const int x = wrap(b3.x + S2 * n2.x, c.g0);
-    const int y = wrap(b3.y + S2 * n2.y, c.g1);
-    const int z = wrap(b3.z + S2 * n2.z, c.g2);
-    return x + c.g0 * (y + c.g1 * z);
+  // With b = b3 folded into the grid once, each digit of b + s'' q'' lies in (-g, 2g) and
+  // needs at most one correction by g; on the linear index the three corrections add to
+  // idx(b) + s'' idx(q'') (iq2 = idx(q''), n2 its digits).
+  const int4 bw = make_int4(wrap(b3.x, c.g0), wrap(b3.y, c.g1), wrap(b3.z, c.g2), 0);
+  const int Bw = bw.x + c.g0 * (bw.y + c.g1 * bw.z);
+  const int G01 = c.g0 * c.g1;
+  auto fold_d = [&](int iq2, int4 n2) {
+    if (S2 < 0)
+      return Bw - iq2 + (bw.x < n2.x ? c.g0 : 0) + (bw.y < n2.y ? G01 : 0) + (bw.z < n2.z ? c.N : 0);
+    return Bw + iq2 - (bw.x + n2.x >= c.g0 ? c.g0 : 0) - (bw.y + n2.y >= c.g1 ? G01 : 0) -
+           (bw.z + n2.z >= c.g2 ? c.N : 0);
   };
   // a queue entry back to (q'', q'''): unpacked, or q''' folded from the grid digits of q''
   // found by division (no index-table load on the critical path)
@@ -658,7 +664,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       int t;
       divmod_small(iq2, c.g0, inv_g0, t, n2.x);
       divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
-      iq3 = fold_d(n2);
+      iq3 = fold_d(iq2, n2);
     }
   };
   for (int k0 = 0; k0 < nk; k0 += KSEG) {
@@ -671,7 +677,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       int iq2 = (k0 * 4 + wave) * GPW + gw;
       int4 d2 = c.qn[min(iq2, c.N - 1)];
       for (int k = k0; k < k1; ++k) {
-        const int iq2c = iq2, iq3c = fold_d(d2);
+        const int iq2c = iq2, iq3c = fold_d(iq2, d2);
         iq2 += 4 * GPW;
         d2.x += DK.x;
         const int cx = d2.x >= c.g0;
@@ -706,7 +712,7 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         if (i < npt && p < nscan) {
           const int4 s = c.qord[p];
           iq2 = s.x;
-          iq3 = fold_d(make_int4(s.y, s.z, s.w, 0));
+          iq3 = fold_d(iq2, make_int4(s.y, s.z, s.w, 0));
           const double4 b2 = c.qbound[iq2], b3 = c.qbound[iq3];
           const double lo = S2 > 0 ? (aw + b2.x) - b3.y : (aw - b2.y) - b3.y;
           const double hi = S2 > 0 ? (aw + b2.y) - b3.x : (aw - b2.x) - b3.x;
