@@ -12,6 +12,8 @@
 //                  V = E3 F E4^T with F = sum_d exp(i s'' q''.d) W''_d, followed by the
 //                  Gaussian, occupation factors and per-lane FP64 accumulation
 //   k_reduce       ordered sum of the per-work-group partial rates
+#include <type_traits>
+
 #include "fp4_internal.h"
 #include "fp4_device.h"
 
@@ -824,12 +826,11 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       // the lane's list entries: single orientations, then mirror pairs with both kept
       // (codes as in gamma_list); their place in the wavefront's list is a prefix sum of the
       // per-lane counts (<= 2 NB < 32) by bit-sliced ballots
+      // (the codes fit 32 bits up to NB = 10; a list that fits one pass needs no bound check)
+      using MT = std::conditional_t<(3 * NB <= 32), unsigned, unsigned long long>;
       const unsigned pr = bA & bB;
-      const unsigned long long m =
-          blk ? ((unsigned long long)(bA & ~pr) | ((unsigned long long)(bB & ~pr) << NB) |
-                 ((unsigned long long)pr << (2 * NB)))
-              : 0ull;
-      const int n = __popcll(m);
+      const MT m = blk ? ((MT)(bA & ~pr) | ((MT)(bB & ~pr) << NB) | ((MT)pr << (2 * NB))) : (MT)0;
+      const int n = sizeof(MT) == 4 ? __popc((unsigned)m) : __popcll((unsigned long long)m);
       int pre = 0, tot = 0;
 #pragma unroll
       for (int bsl = 0; bsl < 5; ++bsl) {
@@ -837,14 +838,25 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
         pre += __popcll(bb & lt) << bsl;
         tot += __popcll(bb) << bsl;
       }
+      auto ctz = [](MT x) {
+        return sizeof(MT) == 4 ? __builtin_ctz((unsigned)x) : __builtin_ctzll((unsigned long long)x);
+      };
       for (int base = 0; base < tot; base += LSEG) {
-        unsigned long long mm = m;
-        int idx = pre;
-        while (mm) {
-          const int b = __builtin_ctzll(mm);
-          mm &= mm - 1ull;
-          if (idx >= base && idx < base + LSEG) Lw[idx - base] = (unsigned short)((lane << 6) | b);
-          ++idx;
+        MT mm = m;
+        int idx = pre - base;
+        if (tot <= LSEG) {
+          while (mm) {
+            const int b = ctz(mm);
+            mm &= mm - (MT)1;
+            Lw[idx++] = (unsigned short)((lane << 6) | b);
+          }
+        } else {
+          while (mm) {
+            const int b = ctz(mm);
+            mm &= mm - (MT)1;
+            if ((unsigned)idx < (unsigned)LSEG) Lw[idx] = (unsigned short)((lane << 6) | b);
+            ++idx;
+          }
         }
         wave_sync();
         gamma_list<R, NB, NT, CH>(c, a, Lw, min(LSEG, tot - base), lane, Xw, Gq, aw, kw, invn, n1, acc);
