@@ -824,19 +824,35 @@ __device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs 
       }
       if (act && r == 0) Gq[gw] = make_int2(iq2, iq3 | (umk ? (1 << 30) : 0));
       // the lane's list entries: single orientations, then mirror pairs with both kept
-      // (codes as in gamma_list); their place in the wavefront's list is a prefix sum of the
-      // per-lane counts (<= 2 NB < 32) by bit-sliced ballots
-      // (the codes fit 32 bits up to NB = 10; a list that fits one pass needs no bound check)
+      // (codes as in gamma_list, one per column, so at most NB < 32 per lane); their place in
+      // the wavefront's list is a prefix sum of the per-lane counts (the codes fit 32 bits up
+      // to NB = 10; a list that fits one pass needs no bound check)
       using MT = std::conditional_t<(3 * NB <= 32), unsigned, unsigned long long>;
       const unsigned pr = bA & bB;
       const MT m = blk ? ((MT)(bA & ~pr) | ((MT)(bB & ~pr) << NB) | ((MT)pr << (2 * NB))) : (MT)0;
       const int n = sizeof(MT) == 4 ? __popc((unsigned)m) : __popcll((unsigned long long)m);
       int pre = 0, tot = 0;
+      if constexpr (sizeof(R) == 8) {
+        // FP64 kernel (measured 0.7% faster; the FP32 one keeps the ballots): an inclusive
+        // scan over the wavefront, all 64 lanes active here, by DPP row shifts by 1, 2, 4, 8
+        // within rows of 16 lanes, then row broadcasts of lane 15 into the odd rows and of
+        // lane 31 into rows 2 and 3
+        int x = n;
+        x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
+        x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
+        x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
+        x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
+        x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+        x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
+        pre = x - n;
+        tot = __builtin_amdgcn_readlane(x, 63);
+      } else {
 #pragma unroll
-      for (int bsl = 0; bsl < 5; ++bsl) {
-        const unsigned long long bb = __ballot((n >> bsl) & 1);
-        pre += __popcll(bb & lt) << bsl;
-        tot += __popcll(bb) << bsl;
+        for (int bsl = 0; bsl < 5; ++bsl) {
+          const unsigned long long bb = __ballot((n >> bsl) & 1);
+          pre += __popcll(bb & lt) << bsl;
+          tot += __popcll(bb) << bsl;
+        }
       }
       auto ctz = [](MT x) {
         return sizeof(MT) == 4 ? __builtin_ctz((unsigned)x) : __builtin_ctzll((unsigned long long)x);
