@@ -278,8 +278,8 @@ template <typename R> constexpr bool VLIST = sizeof(R) == 8;
 //                   E4[j'''][(l,theta)] = conj(E[q'''][j'''][3l+theta])
 // The nb lanes of a group hold one row each and exchange F rows and E4 rows through the
 // group's LDS tile Xg[nb][nb] (all lanes of a group belong to one wavefront).
-template <typename R, int NB, int S2, bool HONLY = false>
-__device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>::T *Ws,
+template <typename R, int NB, bool HONLY = false>
+__device__ __forceinline__ void block_row(const Crystal &c, const typename CT<R>::T *Ws, int S2,
                                           int iq2, int iq3, int r,
                                           typename CT<R>::T *Xg, typename CT<R>::T *Pg,
                                           const int *sg_d, const int *skl,
@@ -400,8 +400,8 @@ struct Acc {
 // The two orientations of a mirror row share s2: d = v'' - v''' of one is the negative of the
 // other's, so their squares and s2 = (dx*dx + dy*dy) + dz*dz are bitwise equal, and only dw
 // is formed twice, each in its own stand-alone order.
-template <int NB, int S2>
-__device__ __forceinline__ void row_bits_cols(const RateArgs &a, double aw, const double4 vr,
+template <int NB>
+__device__ __forceinline__ void row_bits_cols(const RateArgs &a, double aw, int S2, const double4 vr,
                                               double speed, const double4 qb, const double2 *cs,
                                               bool mirror_row, unsigned &b0, unsigned &b1) {
 #pragma clang fp contract(off)
@@ -467,24 +467,67 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
 // entries, so every lane has work while the list lasts.
 // With a.qclass == 3 the sums go by class instead of by channel: normal processes to
 // acc.r[0], Umklapp ones to acc.r[1].
+// The pair (lambda, lambda'): grid digits of q and q', the two modes and their frequencies.
+struct PairIn {
+  int4 nq, nq1;
+  int mu, mu1;
+  double w, w1;
+};
+
+// Per-pair constants of the channels, index 0 for s' = + (++ and +-), 1 for s' = - (--):
+// aw = w s' w', and kw = the channel weight of Eq. tao0 (1/2 for ++ and +-, 1/6 for --)
+// times the prefactor C4/N^2 and 1/(w w') of Eq. 4phgamma (the phase space P4 keeps only the
+// channel weight and 1/N^2).
+struct ChanK {
+  double aw[2];
+  double kw[2];
+  __device__ __forceinline__ ChanK(const Crystal &c, const RateArgs &a, const PairIn &pi) {
+    aw[0] = add_signed(pi.w, pi.w1, 1);
+    aw[1] = add_signed(pi.w, pi.w1, -1);
+    if (a.harmonic == 2) {
+      kw[0] = 0.5 * a.kpref;
+      kw[1] = (1.0 / 6.0) * a.kpref;
+    } else {
+      kw[0] = 0.5 * a.kpref * c.inv_omega[pi.mu] * c.inv_omega[pi.mu1];
+      kw[1] = (1.0 / 6.0) * a.kpref * c.inv_omega[pi.mu] * c.inv_omega[pi.mu1];
+    }
+  }
+};
+
+// Gamma (Eq. 4phgamma) of a compacted list of kept processes of the wavefront's blocks,
+// accumulated into the lane's FP64 partial rates.  Entry i of L is (s << 6) | b for source
+// lane s = (group g, row r) and code b: b < NB is the process (lambda'' = (q''_g, r),
+// lambda''' = (q'''_g, b)), NB <= b < 2 NB the mirrored one (lambda'' = (q'''_g, b - NB),
+// lambda''' = (q''_g, r)), b >= 2 NB both of column b - 2 NB (redistribution or splitting
+// channel, both kept).  The two members of a mirror pair share |V| (V transposed), |v'' - v'''| and so
+// sigma, 1/(w'' w''') and the occupation factor; one evaluation serves both, each with its
+// own dw formed in its stand-alone order and its own Gaussian.  V comes from the group's
+// tile (dense V, or H and a row of E4, see VLIST), (q''_g, q'''_g) from Gq (bit 30 of
+// q'''_g: the block's processes are Umklapp ones; with CH = 3, bit 29: the block is a --
+// one, else a ++ one).  CH = 1 is the redistribution channel; CH = 3 a list whose blocks
+// belong to ++ or to --.  Consecutive lanes take consecutive entries, so every lane has work
+// while the list lasts.  With a.qclass == 3 the sums go by class instead of by channel:
+// normal processes to acc.r[0], Umklapp ones to acc.r[1].
 template <typename R, int NB, int NT, int CH>
 __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
                                            const unsigned short *L, int cnt, int lane,
                                            const typename CT<R>::T *Xw, const int2 *Gq,
-                                           double aw, double kw, const double (&invn)[NT],
+                                           const ChanK &ck, const double (&invn)[NT],
                                            const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
-  constexpr int S2 = (CH == 0) ? 1 : -1;
-  auto decode = [&](int i, int &mu2, int &mu3, int &vi, int &cc, int &m4, bool &pair, bool &umk) {
+  static_assert(CH == 1 || CH == 3, "redistribution, or a list of ++ and -- blocks");
+  auto decode = [&](int i, int &mu2, int &mu3, int &vi, int &cc, int &m4, bool &pair, bool &umk,
+                    bool &neg) {
     const unsigned d = L[i];
     const int s = (int)(d >> 6), b = (int)(d & 63u);
     const int g = s / NB, r = s - g * NB;
     const int2 q = Gq[g];
-    umk = (q.y >> 30) != 0;
+    umk = ((q.y >> 30) & 1) != 0;
+    neg = CH == 3 && ((q.y >> 29) & 1) != 0;
     const bool mir = b >= NB && b < 2 * NB;
     pair = b >= 2 * NB;
     cc = pair ? b - 2 * NB : (mir ? b - NB : b);
-    const int mr = q.x * NB + r, mc = (q.y & 0x3fffffff) * NB + cc;
+    const int mr = q.x * NB + r, mc = (q.y & 0x1fffffff) * NB + cc;
     mu2 = mir ? mc : mr;
     mu3 = mir ? mr : mc;
     vi = g * xtile(NB, sizeof(CR)) + r * NB;
@@ -493,13 +536,18 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
 #pragma unroll 1
   for (int i = lane; i < cnt; i += 64) {
     int mu2, mu3, vi, cc, m4;
-    bool pair, umk;
-    decode(i, mu2, mu3, vi, cc, m4, pair, umk);
+    bool pair, umk, neg;
+    decode(i, mu2, mu3, vi, cc, m4, pair, umk, neg);
+    // s'' = - for +- and --, + for ++; the channel index of the sums
+    const int S2 = (CH == 1 || neg) ? -1 : 1;
+    const int chi = CH == 1 ? 1 : (neg ? 2 : 0);
+    const double aw = neg ? ck.aw[1] : ck.aw[0];
+    const double kw = neg ? ck.kw[1] : ck.kw[0];
     const bool split = a.qclass == 3;
     const ModeRec<NT> p2 = load_rec<NB, NT>(c, a, mu2), p3 = load_rec<NB, NT>(c, a, mu3);
     double dw, s2, dwm = 0.0;
     window_keep(add_signed(aw, p2.m.w, S2), p3.m.w, p2.m, p3.m, a.c_win, dw, s2);
-    if (CH != 0 && pair) {
+    if (pair) {
       // the mirrored member (lambda'' and lambda''' exchanged); its s2 equals s2 exactly
       double s2m;
       window_keep(add_signed(aw, p3.m.w, S2), p2.m.w, p3.m, p2.m, a.c_win, dwm, s2m);
@@ -520,7 +568,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       v2abs = (double)vv.x * (double)vv.x + (double)vv.y * (double)vv.y;
     }
     const double sig2 = a.c_sig * s2;
-    double delta = (CH != 0 && pair) ? 2.0 : 1.0;
+    double delta = pair ? 2.0 : 1.0;
     if (!(sig2 < a.c_min)) {
       // adaptive Gaussian exp(-dw^2/sigma^2) / (sqrt(pi) sigma), 1/sqrt(pi) =
       // 0.5641895835477563; y = 1/sigma from the hardware reciprocal square root refined
@@ -531,7 +579,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       const double y2 = y * y, x0 = (dw * dw) * y2;
       const double e0 = exp(-x0);
       delta = e0 * (0.5641895835477563 * y);
-      if (CH != 0 && pair) {
+      if (pair) {
         // the mirrored member's exponent differs from x0 only by the rounding of its dw
         // (|x0 - x1| <= 1e-8 for any sigma above the floor), so exp(-x1) =
         // e0 exp(d) = e0 (1 + d + d^2/2) to far below the FP64 rounding, d = x0 - x1
@@ -545,341 +593,444 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (t < a.nT) {
+        // occupation factor: (1 + n')(1 + n'') n''' (++), (1 + n') n'' n''' (+-),
+        // n' n'' n''' (--)
         const double n2 = p2.n[t];
         const double n3 = p3.n[t];
         double f;
-        if (CH == 0) f = (1.0 + n1[t]) * (1.0 + n2) * n3;
-        else if (CH == 1) f = (1.0 + n1[t]) * n2 * n3;
-        else f = n1[t] * n2 * n3;
+        if (CH == 1) f = (1.0 + n1[t]) * n2 * n3;
+        else f = (neg ? n1[t] : 1.0 + n1[t]) * (neg ? n2 : 1.0 + n2) * n3;
         const double x = p4 ? base : base * f * invn[t];
         if (split) {
           if (umk) acc.r[1][t] += x;
           else acc.r[0][t] += x;
+        } else if (CH == 1) {
+          acc.r[1][t] += x;
+        } else if (neg) {
+          acc.r[2][t] += x;
         } else {
-          acc.r[CH][t] += x;
+          acc.r[0][t] += x;
         }
       }
     }
-    acc.cnt[CH] += (CH != 0 && pair) ? 2 : 1;
+    const unsigned inc = pair ? 2u : 1u;
+    if (chi == 1) acc.cnt[1] += inc;
+    else if (chi == 2) acc.cnt[2] += inc;
+    else acc.cnt[0] += inc;
   }
 }
 
-// Per wavefront, a.qseg q'' points are queued at a time and a.lseg kept processes evaluated
-// per pass (both set by the host; the autotuner picks them with the q'-chunk).
+// Per wavefront, a.qseg blocks are queued at a time and a.lseg kept processes evaluated per
+// pass (both set by the host; the autotuner picks them with the q'-chunk).
 
-// All blocks (q'') of one channel for fixed lambda, lambda'.  Each wavefront owns a quarter
-// of the q'' points.  Phase 1 compacts the blocks worth contracting into the wavefront's LDS
-// queue in a fixed order (ballot + prefix count): for ++ and -- the blocks with a surviving
-// process, for +- one block of every mirror pair {q'', q'''} (V of the pair members are
-// transposes of each other when the quartet list is symmetric under the slot-3/slot-4
-// exchange, a.mirror; otherwise every q'' block is queued and contracted on its own).
-// Phase 2 lets the wavefront's lane groups contract the queued blocks densely (lane r of a
-// group owns branch row j'' = r) and evaluates the kept processes of the blocks in flight as
-// one compacted list.
+// Where q''' = fold(q + s' q' + s'' q'') lies, for one (s', s''): with b = q + s' q' folded
+// into the grid once, each digit of b + s'' q'' lies in (-g, 2g) and needs at most one
+// correction by g; on the linear index the three corrections add to idx(b) + s'' idx(q'')
+// (iq2 = idx(q''), n2 its digits).
+struct Fold {
+  int4 bw;
+  int Bw;
+  // b = q + s' q'
+  __device__ __forceinline__ Fold(const Crystal &c, const PairIn &pi, int s1) {
+    bw = make_int4(wrap(pi.nq.x + s1 * pi.nq1.x, c.g0), wrap(pi.nq.y + s1 * pi.nq1.y, c.g1),
+                   wrap(pi.nq.z + s1 * pi.nq1.z, c.g2), 0);
+    Bw = bw.x + c.g0 * (bw.y + c.g1 * bw.z);
+  }
+  __device__ __forceinline__ int operator()(const Crystal &c, int s2, int iq2, int4 n2) const {
+    const int G01 = c.g0 * c.g1;
+    if (s2 < 0)
+      return Bw - iq2 + (bw.x < n2.x ? c.g0 : 0) + (bw.y < n2.y ? G01 : 0) + (bw.z < n2.z ? c.N : 0);
+    return Bw + iq2 - (bw.x + n2.x >= c.g0 ? c.g0 : 0) - (bw.y + n2.y >= c.g1 ? G01 : 0) -
+           (bw.z + n2.z >= c.g2 ? c.N : 0);
+  }
+};
+
+// The contraction phase: the wavefront's lane groups take the queued blocks GPW at a time
+// (lane r of a group owns branch row j'' = r), test their rows (the exact window predicate
+// per candidate), contract the blocks with a kept process, and evaluate the kept processes
+// of the blocks in flight as one compacted list.  CH = 1: redistribution blocks; CH = 3: ++
+// and -- blocks (bit 30 of the queue entry: --), whose signs s' = s'' are taken per group.
+// Queue entries hold q'' and q''' packed (15 bits each) on grids of up to 2^15 points (no
+// fold here), q'' alone on larger ones.
 template <typename R, int NB, int NT, int CH>
-__device__ __forceinline__ void channel_blocks(const Crystal &c, const RateArgs &a,
-                                               const typename CT<R>::T *W, int wave, int lane,
-                                               int gw, int r, bool glane,
-                                               typename CT<R>::T *Xg, typename CT<R>::T *Pg,
-                                               const int *sg_d, const int *skl, int *Qw,
+__device__ __forceinline__ void contract_queue(const Crystal &c, const RateArgs &a,
+                                               const typename CT<R>::T *W, int lane, int gw,
+                                               int r, bool glane, typename CT<R>::T *Xg,
+                                               typename CT<R>::T *Pg, const int *sg_d,
+                                               const int *skl, const int *Qw, int cnt,
                                                const typename CT<R>::T *Xw, int2 *Gq,
-                                               unsigned short *Lw, int4 nq, int4 nq1, int mu,
-                                               int mu1, double w, double w1,
+                                               unsigned short *Lw, const PairIn &pi,
                                                const double (&invn)[NT],
                                                const double (&n1)[NT], Acc<NT> &acc) {
   using CR = typename CT<R>::T;
   constexpr int GPW = 64 / NB;
-  constexpr int S1 = (CH == 2) ? -1 : 1;
-  constexpr int S2 = (CH == 0) ? 1 : -1;
-  constexpr bool MIRROR = (CH == 1);
-  // In the redistribution and splitting channels slots 3 and 4 are both conjugated, so for a
-  // slot-3/slot-4 symmetric quartet list the blocks q'' and q''' are transposes: one
-  // contraction serves the mirror pair.  Redistribution queues one block of every pair in
-  // grid order; splitting scans the sorted list and queues the pair from its lower index.
-  const bool mir = CH != 0 && a.mirror != 0;
-  constexpr double WCH = (CH == 2) ? (1.0 / 6.0) : 0.5;
   constexpr unsigned long long GMASK = (1ull << NB) - 1ull;
-  const CR *Ws = W + (S1 > 0 ? 0 : c.ng * WSTR);
-  const double aw = add_signed(w, w1, S1);
-  // weight of the channel (Eq. tao0), prefactor C4/N^2 and 1/(w w') of Eq. 4phgamma
-  // (the phase space P4 keeps only the channel weight and 1/N^2)
-  const double kw = a.harmonic == 2 ? WCH * a.kpref : WCH * a.kpref * c.inv_omega[mu] * c.inv_omega[mu1];
   const unsigned long long lt = (1ull << lane) - 1ull;
-  const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
-  // queue entries hold q'' and q''' packed (15 bits each) on grids of up to 2^15 points, so
-  // the contraction phase does not recompute the fold; larger grids queue q'' alone
+  const int LSEG = a.lseg;
+  const ChanK ck(c, a, pi);
+  const int mu = pi.mu, mu1 = pi.mu1;
   const bool pack = c.N <= 32768;
-  // ++ and --: q'' is scanned in ascending order of its lowest active frequency, and only as
-  // far as a row can pass the window.  A kept process has |dw| <= sqrt(c_win) |v'' - v'''|
-  // <= 2 sqrt(c_win) v_hi, with dw = aw + w'' - w''' (++) or aw - w'' - w''' (--), so its row
-  // frequency w'' is at most thr = w_hi - aw + win (++) or aw - w_lo + win (--).  The margins
-  // are far above the FP64 rounding of the exact test, so no kept process is skipped.
-  // In the splitting channel the same bound holds for w''' (the two slots enter dw alike), so
-  // a block whose q''' has its lowest frequency above thr holds no kept process, and a
-  // mirror pair has both members in the scanned part of the list or no kept process.
-  int nscan = c.N;
-  double thr = 0.0;
-  if (!MIRROR) {
-    const double win = 2.0 * a.sqrt_c_win * c.v_hi * (1.0 + 1e-6) + 1e-9 * (fabs(aw) + c.w_hi) + 1e-12;
-    thr = (S2 > 0 ? c.w_hi - aw : aw - c.w_lo) + win;
-    // count the sorted entries <= thr: whole 64ths of the list first, then the boundary one
-    const int seg = (c.N + 63) >> 6;
-    const bool le = lane * seg < c.N && c.qord_w[min(c.N, (lane + 1) * seg) - 1] <= thr;
-    const int full = __popcll(__ballot(le));
-    nscan = full * seg;
-    for (int i0 = 0; i0 < seg; i0 += 64) {
-      const int i = i0 + lane, p = full * seg + i;
-      const bool b = i < seg && p < c.N && c.qord_w[p] <= thr;
-      nscan += __popcll(__ballot(b));
+  const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
+  for (int e0 = 0; e0 < cnt; e0 += GPW) {
+    const int e = e0 + gw;
+    const bool act = glane && e < cnt;
+    int iq2 = 0, iq3 = 0;
+    bool neg = false;
+    unsigned bA = 0u, bB = 0u;
+    if (act) {
+      const int qv = Qw[e];
+      neg = CH == 3 && ((qv >> 30) & 1) != 0;
+      if (pack) {
+        iq2 = qv & 0x7fff;
+        iq3 = (qv >> 15) & 0x7fff;
+      } else {
+        // grid digits of q'' by division (no index-table load on the critical path)
+        iq2 = qv & 0x3fffffff;
+        int4 n2;
+        int t;
+        divmod_small(iq2, c.g0, inv_g0, t, n2.x);
+        divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
+        iq3 = Fold(c, pi, neg ? -1 : 1)(c, (CH == 1 || neg) ? -1 : 1, iq2, n2);
+      }
+      // lane r reads column record r; the group shares the six through its tile
+      const double4 vc = c.mode4[iq3 * NB + r];
+      double2 *cs = reinterpret_cast<double2 *>(Xg);
+      cs[2 * r] = make_double2(vc.x, vc.y);
+      cs[2 * r + 1] = make_double2(vc.z, vc.w);
+    }
+    // redistribution: s' = +, s'' = -; ++: both +; --: both -
+    const int S1 = neg ? -1 : 1;
+    const int S2 = (CH == 1 || neg) ? -1 : 1;
+    const double aw = neg ? ck.aw[1] : ck.aw[0];
+    // in the redistribution and splitting channels slots 3 and 4 are both conjugated, so
+    // for a slot-3/slot-4 symmetric quartet list the blocks q'' and q''' are transposes:
+    // one contraction serves the mirror pair (its other orientation tested alongside)
+    const bool mir = (CH == 1 || neg) && a.mirror != 0;
+    wave_sync();
+    if (act)
+      row_bits_cols<NB>(a, aw, S2, c.mode4[iq2 * NB + r], c.speed[iq2 * NB + r], c.qbound[iq3],
+                        reinterpret_cast<const double2 *>(Xg), mir && iq2 != iq3, bA, bB);
+    bool umk = false;
+    if (a.qclass != 0 && act) {
+      // normal / Umklapp class of the block (the same for every branch and, for a mirror
+      // pair, both orientations): Q = k(q''') - (k(q) + s' k(q') + s'' k(q'')) on the
+      // first-zone image numerators of the four points
+      const int4 k0 = c.qimg[mu / NB], k1 = c.qimg[mu1 / NB], k2 = c.qimg[iq2], k3 = c.qimg[iq3];
+      umk = (k0.x + S1 * k1.x + S2 * k2.x != k3.x) || (k0.y + S1 * k1.y + S2 * k2.y != k3.y) ||
+            (k0.z + S1 * k1.z + S2 * k2.z != k3.z);
+      if (a.qclass != 3 && umk != (a.qclass == 2)) {
+        bA = 0u;
+        bB = 0u;
+      }
+    }
+    const unsigned long long bal = __ballot((bA | bB) != 0u);
+    const bool blk = act && ((bal >> (gw * NB)) & GMASK) != 0ull;
+    if (blk && r == 0) acc.blocks += 1;
+    if (blk && a.harmonic == 0) {   // the phase spaces take |V|^2 := 1
+      CR V[NB];
+      block_row<R, NB, VLIST<R>>(c, W + (S1 > 0 ? 0 : c.ng * WSTR), S2, iq2, iq3, r, Xg, Pg,
+                                 sg_d, skl, V);
+      if constexpr (!VLIST<R>) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
+      }
+    }
+    if (act && r == 0) Gq[gw] = make_int2(iq2, iq3 | (neg ? (1 << 29) : 0) | (umk ? (1 << 30) : 0));
+    // the lane's list entries: single orientations, then mirror pairs with both kept
+    // (codes as in gamma_list, one per column, so at most NB < 32 per lane); their place in
+    // the wavefront's list is a prefix sum of the per-lane counts (the codes fit 32 bits up
+    // to NB = 10; a list that fits one pass needs no bound check)
+    using MT = std::conditional_t<(3 * NB <= 32), unsigned, unsigned long long>;
+    const unsigned pr = bA & bB;
+    const MT m = blk ? ((MT)(bA & ~pr) | ((MT)(bB & ~pr) << NB) | ((MT)pr << (2 * NB))) : (MT)0;
+    const int n = sizeof(MT) == 4 ? __popc((unsigned)m) : __popcll((unsigned long long)m);
+    int pre = 0, tot = 0;
+    if constexpr (sizeof(R) == 8) {
+      // FP64 kernel (measured 0.7% faster; the FP32 one keeps the ballots): an inclusive
+      // scan over the wavefront, all 64 lanes active here, by DPP row shifts by 1, 2, 4, 8
+      // within rows of 16 lanes, then row broadcasts of lane 15 into the odd rows and of
+      // lane 31 into rows 2 and 3
+      int x = n;
+      x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
+      x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
+      x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
+      x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
+      x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+      x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
+      pre = x - n;
+      tot = __builtin_amdgcn_readlane(x, 63);
+    } else {
+#pragma unroll
+      for (int bsl = 0; bsl < 5; ++bsl) {
+        const unsigned long long bb = __ballot((n >> bsl) & 1);
+        pre += __popcll(bb & lt) << bsl;
+        tot += __popcll(bb) << bsl;
+      }
+    }
+    auto ctz = [](MT x) {
+      return sizeof(MT) == 4 ? __builtin_ctz((unsigned)x) : __builtin_ctzll((unsigned long long)x);
+    };
+    for (int base = 0; base < tot; base += LSEG) {
+      MT mm = m;
+      int idx = pre - base;
+      if (tot <= LSEG) {
+        while (mm) {
+          const int b = ctz(mm);
+          mm &= mm - (MT)1;
+          Lw[idx++] = (unsigned short)((lane << 6) | b);
+        }
+      } else {
+        while (mm) {
+          const int b = ctz(mm);
+          mm &= mm - (MT)1;
+          if ((unsigned)idx < (unsigned)LSEG) Lw[idx] = (unsigned short)((lane << 6) | b);
+          ++idx;
+        }
+      }
+      wave_sync();
+      gamma_list<R, NB, NT, CH>(c, a, Lw, min(LSEG, tot - base), lane, Xw, Gq, ck, invn, n1, acc);
+      wave_sync();
     }
   }
-  // q'' (or the sorted list) is dealt to the wavefronts in rounds of GPW consecutive points, so that every
-  // wavefront sees the whole range (the mirror-pair members are not spread evenly over it)
-  const int nk = (nscan + 4 * GPW - 1) / (4 * GPW);
+  wave_sync();
+}
+
+// Redistribution (+-) blocks of one pair (lambda, lambda'): every q'' in grid order, one
+// block of each mirror pair {q'', q'''} (V of the pair members are transposes of each other
+// when the quartet list is symmetric under the slot-3/slot-4 exchange, a.mirror; otherwise
+// every q'' block is queued and contracted on its own).  q'' is dealt to the wavefronts in
+// rounds of GPW consecutive points, so that every wavefront sees the whole grid; each
+// wavefront queues a segment of rounds in a fixed order (ballot + prefix count), then
+// contracts the queue.
+template <typename R, int NB, int NT>
+__device__ __forceinline__ void redistribution_blocks(
+    const Crystal &c, const RateArgs &a, const typename CT<R>::T *W, int wave, int lane, int gw,
+    int r, bool glane, typename CT<R>::T *Xg, typename CT<R>::T *Pg, const int *sg_d,
+    const int *skl, int *Qw, const typename CT<R>::T *Xw, int2 *Gq, unsigned short *Lw,
+    const PairIn &pi, const double (&invn)[NT], const double (&n1)[NT], Acc<NT> &acc) {
+  constexpr int GPW = 64 / NB;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const bool pack = c.N <= 32768;
+  const bool mir = a.mirror != 0;
+  const Fold fp(c, pi, 1);
+  const int nk = (c.N + 4 * GPW - 1) / (4 * GPW);
   const int KSEG = a.qseg / GPW;
-  const int LSEG = a.lseg;
-  // the column point is fold(b3 + s'' q''), b3 = q + s' q'; DK = grid digits of the
-  // per-round step 4 GPW of q''
-  const int4 b3 = make_int4(nq.x + S1 * nq1.x, nq.y + S1 * nq1.y, nq.z + S1 * nq1.z, 0);
+  // grid digits of the per-round step 4 GPW of q''
   const int4 DK = make_int4((4 * GPW) % c.g0, ((4 * GPW) / c.g0) % c.g1, (4 * GPW) / (c.g0 * c.g1), 0);
-  // With b = b3 folded into the grid once, each digit of b + s'' q'' lies in (-g, 2g) and
-  // needs at most one correction by g; on the linear index the three corrections add to
-  // idx(b) + s'' idx(q'') (iq2 = idx(q''), n2 its digits).
-  const int4 bw = make_int4(wrap(b3.x, c.g0), wrap(b3.y, c.g1), wrap(b3.z, c.g2), 0);
-  const int Bw = bw.x + c.g0 * (bw.y + c.g1 * bw.z);
-  const int G01 = c.g0 * c.g1;
-  auto fold_d = [&](int iq2, int4 n2) {
-    if (S2 < 0)
-      return Bw - iq2 + (bw.x < n2.x ? c.g0 : 0) + (bw.y < n2.y ? G01 : 0) + (bw.z < n2.z ? c.N : 0);
-    return Bw + iq2 - (bw.x + n2.x >= c.g0 ? c.g0 : 0) - (bw.y + n2.y >= c.g1 ? G01 : 0) -
-           (bw.z + n2.z >= c.g2 ? c.N : 0);
-  };
-  // a queue entry back to (q'', q'''): unpacked, or q''' folded from the grid digits of q''
-  // found by division (no index-table load on the critical path)
-  auto unpack_q = [&](int qv, int &iq2, int &iq3) {
+  for (int k0 = 0; k0 < nk; k0 += KSEG) {
+    const int k1 = min(nk, k0 + KSEG);
+    int cnt = 0;
+    // the grid digits of q'' advance arithmetically by DK per round (no index-table load)
+    int iq2 = (k0 * 4 + wave) * GPW + gw;
+    int4 d2 = c.qn[min(iq2, c.N - 1)];
+    for (int k = k0; k < k1; ++k) {
+      const int iq2c = iq2, iq3c = fp(c, -1, iq2, d2);
+      iq2 += 4 * GPW;
+      d2.x += DK.x;
+      const int cx = d2.x >= c.g0;
+      d2.x -= cx ? c.g0 : 0;
+      d2.y += DK.y + cx;
+      const int cy = d2.y >= c.g1;
+      d2.y -= cy ? c.g1 : 0;
+      d2.z += DK.z + cy;
+      const bool lead = glane && iq2c < c.N && (!mir || iq2c <= iq3c) && r == 0;
+      const unsigned long long lb = __ballot(lead);
+      if (lead) Qw[cnt + __popcll(lb & lt)] = pack ? (iq2c | (iq3c << 15)) : iq2c;
+      cnt += __popcll(lb);
+    }
+    wave_sync();
+    contract_queue<R, NB, NT, 1>(c, a, W, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, cnt, Xw, Gq,
+                                 Lw, pi, invn, n1, acc);
+  }
+}
+
+// The threshold of the scan of ++ (CH = 0) or -- (CH = 2) and its length: the sorted entries
+// <= thr, counted in whole 64ths of the list first, then in the boundary one.
+template <int CH>
+__device__ __forceinline__ double sorted_thr(const Crystal &c, const RateArgs &a,
+                                             const PairIn &pi) {
+  constexpr int S2 = (CH == 0) ? 1 : -1;
+  const double aw = add_signed(pi.w, pi.w1, S2);
+  const double win = 2.0 * a.sqrt_c_win * c.v_hi * (1.0 + 1e-6) + 1e-9 * (fabs(aw) + c.w_hi) + 1e-12;
+  return (S2 > 0 ? c.w_hi - aw : aw - c.w_lo) + win;
+}
+
+template <int CH>
+__device__ __forceinline__ int sorted_scan(const Crystal &c, const RateArgs &a, int lane,
+                                           const PairIn &pi) {
+  const double thr = sorted_thr<CH>(c, a, pi);
+  const int seg = (c.N + 63) >> 6;
+  const bool le = lane * seg < c.N && c.qord_w[min(c.N, (lane + 1) * seg) - 1] <= thr;
+  const int full = __popcll(__ballot(le));
+  int nscan = full * seg;
+  for (int i0 = 0; i0 < seg; i0 += 64) {
+    const int i = i0 + lane, p = full * seg + i;
+    const bool b = i < seg && p < c.N && c.qord_w[p] <= thr;
+    nscan += __popcll(__ballot(b));
+  }
+  return nscan;
+}
+
+// One segment, rounds [k0, k1), of the scan of ++ (CH = 0) or -- (CH = 2): the blocks with
+// a kept process are appended to the queue (tagged with bit 30 for --).  The sorted list is
+// dealt to the wavefronts in rounds of GPW consecutive points.
+template <int NB, int CH>
+__device__ __forceinline__ void sorted_segment(const Crystal &c, const RateArgs &a, int wave,
+                                               int lane, int gw, int r, bool glane,
+                                               double2 *cs, int *Qw, int &cnt,
+                                               const PairIn &pi, int nscan, int k0, int k1) {
+  constexpr int GPW = 64 / NB;
+  constexpr int S2 = (CH == 0) ? 1 : -1;
+  constexpr unsigned long long GMASK = (1ull << NB) - 1ull;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const bool pack = c.N <= 32768;
+  const unsigned tag = CH == 2 ? (1u << 30) : 0u;
+  // splitting with mirror pairs: the pair {q'', q'''} is taken from its lower index, with
+  // both orientations tested
+  const bool mir = CH == 2 && a.mirror != 0;
+  const Fold fold(c, pi, S2);
+  const double aw = add_signed(pi.w, pi.w1, S2);
+  // (formed again here rather than carried across the contraction: fewer live registers)
+  const double thr = sorted_thr<CH>(c, a, pi);
+  const float inv_g0 = 1.0f / (float)c.g0, inv_g1 = 1.0f / (float)c.g1;
+  const int npt = (k1 - k0) * GPW;
+  auto staged = [&](int v, int &iq2, int &iq3) {
     if (pack) {
-      iq2 = qv & 0x7fff;
-      iq3 = qv >> 15;
+      iq2 = v & 0x7fff;
+      iq3 = v >> 15;
     } else {
-      iq2 = qv;
+      iq2 = v;
       int4 n2;
       int t;
       divmod_small(iq2, c.g0, inv_g0, t, n2.x);
       divmod_small(t, c.g1, inv_g1, n2.z, n2.y);
-      iq3 = fold_d(iq2, n2);
+      iq3 = fold(c, S2, iq2, n2);
     }
   };
-  for (int k0 = 0; k0 < nk; k0 += KSEG) {
-    const int k1 = min(nk, k0 + KSEG);
-    // phase 1: queue
-    int cnt = 0;
-    if constexpr (MIRROR) {
-      // every q'' in grid order, one block of each mirror pair; the grid digits of q''
-      // advance arithmetically by DK per round (no index-table load)
-      int iq2 = (k0 * 4 + wave) * GPW + gw;
-      int4 d2 = c.qn[min(iq2, c.N - 1)];
-      for (int k = k0; k < k1; ++k) {
-        const int iq2c = iq2, iq3c = fold_d(iq2, d2);
-        iq2 += 4 * GPW;
-        d2.x += DK.x;
-        const int cx = d2.x >= c.g0;
-        d2.x -= cx ? c.g0 : 0;
-        d2.y += DK.y + cx;
-        const int cy = d2.y >= c.g1;
-        d2.y -= cy ? c.g1 : 0;
-        d2.z += DK.z + cy;
-        const bool lead = glane && iq2c < c.N && (!mir || iq2c <= iq3c) && r == 0;
-        const unsigned long long lb = __ballot(lead);
-        if (lead) Qw[cnt + __popcll(lb & lt)] = pack ? (iq2c | (iq3c << 15)) : iq2c;
-        cnt += __popcll(lb);
-      }
-    } else {
-      // stage A: every lane tests one point of the segment's part of the sorted list against
-      // a bound on its whole block: dw of any process of (q'', q''') lies in
-      // [aw + w''_min - w'''_max, aw + w''_max - w'''_min] (++) or
-      // [aw - w''_max - w'''_max, aw - w''_min - w'''_min] (--), and a kept one has
-      // |dw| <= sqrt(c_win) (v''_max + v'''_max); the interval is widened by 1e-9 of the
-      // frequencies entering it (far above its FP64 rounding) and the bound by 1e-6, so no
-      // block with a kept process is dropped.  In the splitting channel the interval is the
-      // same for both orientations of a mirror pair.  The survivors are compacted into Qw.
-      const double bmar = 1e-9 * (fabs(aw) + 2.0 * c.w_hi) + 1e-12;
-      const int npt = (k1 - k0) * GPW;
-      int ns = 0;
-      for (int i0 = 0; i0 < npt; i0 += 64) {
-        const int i = i0 + lane;
-        const int kr = i / GPW;
-        const int p = ((k0 + kr) * 4 + wave) * GPW + (i - kr * GPW);
-        bool sv = false;
-        int iq2 = 0, iq3 = 0;
-        if (i < npt && p < nscan) {
-          const int4 s = c.qord[p];
-          iq2 = s.x;
-          iq3 = fold_d(iq2, make_int4(s.y, s.z, s.w, 0));
-          const double4 b2 = c.qbound[iq2], b3 = c.qbound[iq3];
-          const double lo = S2 > 0 ? (aw + b2.x) - b3.y : (aw - b2.y) - b3.y;
-          const double hi = S2 > 0 ? (aw + b2.y) - b3.x : (aw - b2.x) - b3.x;
-          const double lim = a.sqrt_c_win * (b2.z + b3.z) * (1.0 + 1e-6) + bmar;
-          sv = !(lo > lim) && !(hi < -lim);
-          // splitting with mirror pairs: the pair {q'', q'''} is taken from its lower index,
-          // with both orientations tested; a q''' outside the scanned part holds no kept
-          // process
-          if (mir) sv = sv && iq2 <= iq3 && b3.x <= thr;
-        }
-        const unsigned long long bal = __ballot(sv);
-        if (sv) Qw[ns + __popcll(bal & lt)] = pack ? (iq2 | (iq3 << 15)) : iq2;
-        ns += __popcll(bal);
-      }
-      wave_sync();
-      // stage B: the lane groups take the surviving points GPW at a time and test their rows
-      // against the six columns (the next round's records are fetched while the current one
-      // is tested); the blocks with a kept process are queued in place, below the entries
-      // still to be read
-      int e = gw;
-      bool live = glane && e < ns;
-      int iq2 = 0, iq3 = 0;
-      if (live) unpack_q(Qw[e], iq2, iq3);
-      const double4 z4 = make_double4(0.0, 0.0, 0.0, 0.0);
-      double4 vr = live ? c.mode4[iq2 * NB + r] : z4;
-      double sp = live ? c.speed[iq2 * NB + r] : 0.0;
-      double4 qb = live ? c.qbound[iq3] : z4;
-      double4 vc = live ? c.mode4[iq3 * NB + r] : z4;
-      double2 *cs = reinterpret_cast<double2 *>(Xg);
-      for (int j0 = 0; j0 < ns; j0 += GPW) {
-        const bool livec = live;
-        const int iq2c = iq2, iq3c = iq3;
-        const double4 vrc = vr, qbc = qb;
-        const double spc = sp;
-        // lane r holds column record r of the round; the group shares the six through its tile
-        if (livec) {
-          cs[2 * r] = make_double2(vc.x, vc.y);
-          cs[2 * r + 1] = make_double2(vc.z, vc.w);
-        }
-        e += GPW;
-        live = glane && e < ns;
-        if (live) {
-          unpack_q(Qw[e], iq2, iq3);
-          vr = c.mode4[iq2 * NB + r];
-          sp = c.speed[iq2 * NB + r];
-          qb = c.qbound[iq3];
-          vc = c.mode4[iq3 * NB + r];
-        }
-        wave_sync();
-        bool keep = false;
-        if (livec) {
-          unsigned b0, b1;
-          row_bits_cols<NB, S2>(a, aw, vrc, spc, qbc, cs, mir && iq2c != iq3c, b0, b1);
-          const unsigned long long bal = __ballot((b0 | b1) != 0u);
-          keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
-        }
-        wave_sync();
-        const bool lead = keep && r == 0;
-        const unsigned long long lb = __ballot(lead);
-        if (lead) Qw[cnt + __popcll(lb & lt)] = pack ? (iq2c | (iq3c << 15)) : iq2c;
-        cnt += __popcll(lb);
-      }
+  const int c0 = cnt;
+  // stage A: every lane tests one point of the segment's part of the sorted list against
+  // a bound on its whole block: dw of any process of (q'', q''') lies in
+  // [aw + w''_min - w'''_max, aw + w''_max - w'''_min] (++) or
+  // [aw - w''_max - w'''_max, aw - w''_min - w'''_min] (--), and a kept one has
+  // |dw| <= sqrt(c_win) (v''_max + v'''_max); the interval is widened by 1e-9 of the
+  // frequencies entering it (far above its FP64 rounding) and the bound by 1e-6, so no
+  // block with a kept process is dropped.  In the splitting channel the interval is the
+  // same for both orientations of a mirror pair.  The survivors are staged at Qw[c0...].
+  const double bmar = 1e-9 * (fabs(aw) + 2.0 * c.w_hi) + 1e-12;
+  int ns = 0;
+  for (int i0 = 0; i0 < npt; i0 += 64) {
+    const int i = i0 + lane;
+    const int kr = i / GPW;
+    const int p = ((k0 + kr) * 4 + wave) * GPW + (i - kr * GPW);
+    bool sv = false;
+    int iq2 = 0, iq3 = 0;
+    if (i < npt && p < nscan) {
+      const int4 s = c.qord[p];
+      iq2 = s.x;
+      iq3 = fold(c, S2, iq2, make_int4(s.y, s.z, s.w, 0));
+      const double4 b2 = c.qbound[iq2], b3 = c.qbound[iq3];
+      const double lo = S2 > 0 ? (aw + b2.x) - b3.y : (aw - b2.y) - b3.y;
+      const double hi = S2 > 0 ? (aw + b2.y) - b3.x : (aw - b2.x) - b3.x;
+      const double lim = a.sqrt_c_win * (b2.z + b3.z) * (1.0 + 1e-6) + bmar;
+      sv = !(lo > lim) && !(hi < -lim);
+      // a mirror pair is taken from its lower index; a q''' outside the scanned part
+      // holds no kept process
+      if (mir) sv = sv && iq2 <= iq3 && b3.x <= thr;
+    }
+    const unsigned long long bal = __ballot(sv);
+    if (sv) Qw[c0 + ns + __popcll(bal & lt)] = pack ? (iq2 | (iq3 << 15)) : iq2;
+    ns += __popcll(bal);
+  }
+  wave_sync();
+  // stage B: the lane groups take the surviving points GPW at a time and test their rows
+  // against the six columns (the next round's records are fetched while the current one
+  // is tested); the blocks with a kept process are queued in place, below the entries
+  // still to be read
+  int e = gw;
+  bool live = glane && e < ns;
+  int iq2 = 0, iq3 = 0;
+  if (live) staged(Qw[c0 + e], iq2, iq3);
+  const double4 z4 = make_double4(0.0, 0.0, 0.0, 0.0);
+  double4 vr = live ? c.mode4[iq2 * NB + r] : z4;
+  double sp = live ? c.speed[iq2 * NB + r] : 0.0;
+  double4 qb = live ? c.qbound[iq3] : z4;
+  double4 vc = live ? c.mode4[iq3 * NB + r] : z4;
+  for (int j0 = 0; j0 < ns; j0 += GPW) {
+    const bool livec = live;
+    const int iq2c = iq2, iq3c = iq3;
+    const double4 vrc = vr, qbc = qb;
+    const double spc = sp;
+    // lane r holds column record r of the round; the group shares the six through its tile
+    if (livec) {
+      cs[2 * r] = make_double2(vc.x, vc.y);
+      cs[2 * r + 1] = make_double2(vc.z, vc.w);
+    }
+    e += GPW;
+    live = glane && e < ns;
+    if (live) {
+      staged(Qw[c0 + e], iq2, iq3);
+      vr = c.mode4[iq2 * NB + r];
+      sp = c.speed[iq2 * NB + r];
+      qb = c.qbound[iq3];
+      vc = c.mode4[iq3 * NB + r];
     }
     wave_sync();
-    // phase 2: contract the queued blocks, GPW at a time (one per lane group), then
-    // evaluate their kept processes as one compacted list
-    for (int e0 = 0; e0 < cnt; e0 += GPW) {
-      const int e = e0 + gw;
-      const bool act = glane && e < cnt;
-      int iq2 = 0, iq3 = 0;
-      unsigned bA = 0u, bB = 0u;
-      if (act) {
-        unpack_q(Qw[e], iq2, iq3);
-        // lane r reads column record r; the group shares the six through its tile
-        const double4 vc = c.mode4[iq3 * NB + r];
-        double2 *cs = reinterpret_cast<double2 *>(Xg);
-        cs[2 * r] = make_double2(vc.x, vc.y);
-        cs[2 * r + 1] = make_double2(vc.z, vc.w);
-      }
-      wave_sync();
-      if (act)
-        row_bits_cols<NB, S2>(a, aw, c.mode4[iq2 * NB + r], c.speed[iq2 * NB + r], c.qbound[iq3],
-                              reinterpret_cast<const double2 *>(Xg), mir && iq2 != iq3, bA, bB);
-      bool umk = false;
-      if (a.qclass != 0 && act) {
-        // normal / Umklapp class of the block (the same for every branch and, for a mirror
-        // pair, both orientations): Q = k(q''') - (k(q) + s' k(q') + s'' k(q'')) on the
-        // first-zone image numerators of the four points
-        const int4 k0 = c.qimg[mu / NB], k1 = c.qimg[mu1 / NB], k2 = c.qimg[iq2], k3 = c.qimg[iq3];
-        umk = (k0.x + S1 * k1.x + S2 * k2.x != k3.x) || (k0.y + S1 * k1.y + S2 * k2.y != k3.y) ||
-              (k0.z + S1 * k1.z + S2 * k2.z != k3.z);
-        if (a.qclass != 3 && umk != (a.qclass == 2)) {
-          bA = 0u;
-          bB = 0u;
-        }
-      }
-      const unsigned long long bal = __ballot((bA | bB) != 0u);
-      const bool blk = act && ((bal >> (gw * NB)) & GMASK) != 0ull;
-      if (blk && r == 0) acc.blocks += 1;
-      if (blk && a.harmonic == 0) {   // the phase spaces take |V|^2 := 1
-        CR V[NB];
-        block_row<R, NB, S2, VLIST<R>>(c, Ws, iq2, iq3, r, Xg, Pg, sg_d, skl, V);
-        if constexpr (!VLIST<R>) {
-#pragma unroll
-          for (int cc = 0; cc < NB; ++cc) Xg[r * NB + cc] = V[cc];
-        }
-      }
-      if (act && r == 0) Gq[gw] = make_int2(iq2, iq3 | (umk ? (1 << 30) : 0));
-      // the lane's list entries: single orientations, then mirror pairs with both kept
-      // (codes as in gamma_list, one per column, so at most NB < 32 per lane); their place in
-      // the wavefront's list is a prefix sum of the per-lane counts (the codes fit 32 bits up
-      // to NB = 10; a list that fits one pass needs no bound check)
-      using MT = std::conditional_t<(3 * NB <= 32), unsigned, unsigned long long>;
-      const unsigned pr = bA & bB;
-      const MT m = blk ? ((MT)(bA & ~pr) | ((MT)(bB & ~pr) << NB) | ((MT)pr << (2 * NB))) : (MT)0;
-      const int n = sizeof(MT) == 4 ? __popc((unsigned)m) : __popcll((unsigned long long)m);
-      int pre = 0, tot = 0;
-      if constexpr (sizeof(R) == 8) {
-        // FP64 kernel (measured 0.7% faster; the FP32 one keeps the ballots): an inclusive
-        // scan over the wavefront, all 64 lanes active here, by DPP row shifts by 1, 2, 4, 8
-        // within rows of 16 lanes, then row broadcasts of lane 15 into the odd rows and of
-        // lane 31 into rows 2 and 3
-        int x = n;
-        x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
-        x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
-        x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
-        x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
-        x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
-        x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
-        pre = x - n;
-        tot = __builtin_amdgcn_readlane(x, 63);
-      } else {
-#pragma unroll
-        for (int bsl = 0; bsl < 5; ++bsl) {
-          const unsigned long long bb = __ballot((n >> bsl) & 1);
-          pre += __popcll(bb & lt) << bsl;
-          tot += __popcll(bb) << bsl;
-        }
-      }
-      auto ctz = [](MT x) {
-        return sizeof(MT) == 4 ? __builtin_ctz((unsigned)x) : __builtin_ctzll((unsigned long long)x);
-      };
-      for (int base = 0; base < tot; base += LSEG) {
-        MT mm = m;
-        int idx = pre - base;
-        if (tot <= LSEG) {
-          while (mm) {
-            const int b = ctz(mm);
-            mm &= mm - (MT)1;
-            Lw[idx++] = (unsigned short)((lane << 6) | b);
-          }
-        } else {
-          while (mm) {
-            const int b = ctz(mm);
-            mm &= mm - (MT)1;
-            if ((unsigned)idx < (unsigned)LSEG) Lw[idx] = (unsigned short)((lane << 6) | b);
-            ++idx;
-          }
-        }
-        wave_sync();
-        gamma_list<R, NB, NT, CH>(c, a, Lw, min(LSEG, tot - base), lane, Xw, Gq, aw, kw, invn, n1, acc);
-        wave_sync();
-      }
+    bool keep = false;
+    if (livec) {
+      unsigned b0, b1;
+      row_bits_cols<NB>(a, aw, S2, vrc, spc, qbc, cs, mir && iq2c != iq3c, b0, b1);
+      const unsigned long long bal = __ballot((b0 | b1) != 0u);
+      keep = ((bal >> (gw * NB)) & GMASK) != 0ull;
     }
     wave_sync();
+    const bool lead = keep && r == 0;
+    const unsigned long long lb = __ballot(lead);
+    if (lead) Qw[cnt + __popcll(lb & lt)] = (int)((pack ? (unsigned)(iq2c | (iq3c << 15)) : (unsigned)iq2c) | tag);
+    cnt += __popcll(lb);
+  }
+  wave_sync();
+}
+
+// Recombination (++) and splitting (--) blocks of one pair: q'' is scanned in ascending order
+// of its lowest active frequency, and only as far as a row can pass the window.  A kept
+// process has |dw| <= sqrt(c_win) |v'' - v'''| <= 2 sqrt(c_win) v_hi, with
+// dw = aw + w'' - w''' (++) or aw - w'' - w''' (--), so its row frequency w'' is at most
+// thr = w_hi - aw + win (++) or aw - w_lo + win (--).  The margins are far above the FP64
+// rounding of the exact test, so no kept process is skipped.  In the splitting channel the
+// same bound holds for w''' (the two slots enter dw alike), so a block whose q''' has its
+// lowest frequency above thr holds no kept process, and a mirror pair has both members in
+// the scanned part of the list or no kept process.  The blocks with a kept process of both
+// channels go to one queue, contracted when the next segment would not fit and at the end,
+// so the few blocks of the two channels fill common rounds (one call site of the
+// contraction).
+template <typename R, int NB, int NT>
+__device__ __forceinline__ void sorted_blocks(
+    const Crystal &c, const RateArgs &a, const typename CT<R>::T *W, int wave, int lane, int gw,
+    int r, bool glane, typename CT<R>::T *Xg, typename CT<R>::T *Pg, const int *sg_d,
+    const int *skl, int *Qw, const typename CT<R>::T *Xw, int2 *Gq, unsigned short *Lw,
+    const PairIn &pi, const double (&invn)[NT], const double (&n1)[NT], Acc<NT> &acc) {
+  constexpr int GPW = 64 / NB;
+  const int KSEG = a.qseg / GPW;
+  const int ns0 = (a.mask & 1u) ? sorted_scan<0>(c, a, lane, pi) : 0;
+  const int ns2 = (a.mask & 4u) ? sorted_scan<2>(c, a, lane, pi) : 0;
+  const int nk0 = (ns0 + 4 * GPW - 1) / (4 * GPW), nk2 = (ns2 + 4 * GPW - 1) / (4 * GPW);
+  const int sg0 = (nk0 + KSEG - 1) / KSEG, sg2 = (nk2 + KSEG - 1) / KSEG;
+  double2 *cs = reinterpret_cast<double2 *>(Xg);
+  int cnt = 0;
+  for (int sgi = 0; sgi <= sg0 + sg2; ++sgi) {
+    const bool last = sgi == sg0 + sg2;
+    const bool m2 = sgi >= sg0;
+    const int k0 = (m2 ? sgi - sg0 : sgi) * KSEG;
+    const int k1 = min(m2 ? nk2 : nk0, k0 + KSEG);
+    const int npt = last ? 0 : (k1 - k0) * GPW;
+    if (last || cnt + npt > a.qseg) {
+      contract_queue<R, NB, NT, 3>(c, a, W, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, cnt, Xw,
+                                   Gq, Lw, pi, invn, n1, acc);
+      cnt = 0;
+    }
+    if (last) break;
+    if (m2) sorted_segment<NB, 2>(c, a, wave, lane, gw, r, glane, cs, Qw, cnt, pi, ns2, k0, k1);
+    else sorted_segment<NB, 0>(c, a, wave, lane, gw, r, glane, cs, Qw, cnt, pi, ns0, k0, k1);
   }
 }
 
@@ -947,12 +1098,11 @@ __device__ __forceinline__ void rate_body(const Crystal &c, const RateArgs &a, i
         double n1[NT];
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) n1[tt] = (tt < a.nT) ? uniform_d(a.occ[(size_t)tt * c.N * NB + mu1]) : 0.0;
-        if (a.mask & 1u)
-          channel_blocks<R, NB, NT, 0>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+        const PairIn pi{nq, nq1, mu, mu1, w, w1};
+        if (a.mask & 5u)
+          sorted_blocks<R, NB, NT>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, pi, invn, n1, acc);
         if (a.mask & 2u)
-          channel_blocks<R, NB, NT, 1>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
-        if (a.mask & 4u)
-          channel_blocks<R, NB, NT, 2>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, nq, nq1, mu, mu1, w, w1, invn, n1, acc);
+          redistribution_blocks<R, NB, NT>(c, a, W, wave, lane, gw, r, glane, Xg, Pg, sg_d, skl, Qw, Xw, Gqw, Lw, pi, invn, n1, acc);
       }
     }
   }
@@ -1127,8 +1277,7 @@ __global__ __launch_bounds__(64) void k_debug_v(Crystal c, const int *quads, con
   const int iq3 = x + c.g0 * (y + c.g1 * z);
   CR V[NB];
   const CR *Ws = W + (s1 > 0 ? 0 : c.ng * WSTR);
-  if (s2 > 0) block_row<R, NB, 1>(c, Ws, iq2, iq3, tid, Xg, Pg, sg_d, skl, V);
-  else block_row<R, NB, -1>(c, Ws, iq2, iq3, tid, Xg, Pg, sg_d, skl, V);
+  block_row<R, NB>(c, Ws, s2, iq2, iq3, tid, Xg, Pg, sg_d, skl, V);
   if (tid == j2) {
 #pragma unroll
     for (int cc = 0; cc < NB; ++cc)
