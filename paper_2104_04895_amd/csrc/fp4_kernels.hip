@@ -467,6 +467,32 @@ __device__ __forceinline__ ModeRec<NT> load_rec(const Crystal &c, const RateArgs
 // entries, so every lane has work while the list lasts.
 // With a.qclass == 3 the sums go by class instead of by channel: normal processes to
 // acc.r[0], Umklapp ones to acc.r[1].
+// exp(-x) for x >= 0 (in the Gaussian x <= window_w^2, a few units): x = k ln2 - t with
+// k = rint(x / ln2) and |t| <= ln2 / 2, reduced in two steps after Cody and Waite with ln2
+// split into a 40-bit head (k ln2_hi exact for |k| < 2^13) and the rest; exp(t) by its
+// Taylor series to t^12 (truncation below 2e-16 relative for |t| <= ln2 / 2, Horner in
+// FP64), scaled by 2^-k.  x is capped at 800, where exp(-x) is 0 in FP64 already.
+__device__ __forceinline__ double exp_neg(double x) {
+  x = fmin(x, 800.0);
+  const double k = rint(x * 1.4426950408889634);
+  double t = fma(k, 0.6931471805592082, -x);
+  t = fma(k, 7.371002565167799e-13, t);
+  double p = 2.08767569878681e-09;           // 1/12!
+  p = fma(p, t, 2.505210838544172e-08);      // 1/11!
+  p = fma(p, t, 2.755731922398589e-07);      // 1/10!
+  p = fma(p, t, 2.7557319223985893e-06);     // 1/9!
+  p = fma(p, t, 2.48015873015873e-05);       // 1/8!
+  p = fma(p, t, 0.0001984126984126984);      // 1/7!
+  p = fma(p, t, 0.001388888888888889);       // 1/6!
+  p = fma(p, t, 0.008333333333333333);       // 1/5!
+  p = fma(p, t, 0.041666666666666664);       // 1/4!
+  p = fma(p, t, 0.16666666666666666);        // 1/3!
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  return ldexp(p, -(int)k);
+}
+
 // The pair (lambda, lambda'): grid digits of q and q', the two modes and their frequencies.
 struct PairIn {
   int4 nq, nq1;
@@ -577,7 +603,7 @@ __device__ __forceinline__ void gamma_list(const Crystal &c, const RateArgs &a,
       y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
       y = fma(0.5 * y, fma(-sig2 * y, y, 1.0), y);
       const double y2 = y * y, x0 = (dw * dw) * y2;
-      const double e0 = exp(-x0);
+      const double e0 = exp_neg(x0);
       delta = e0 * (0.5641895835477563 * y);
       if (pair) {
         // the mirrored member's exponent differs from x0 only by the rounding of its dw
