@@ -824,9 +824,11 @@ __device__ __forceinline__ void contract_queue(const Crystal &c, const RateArgs 
 // Redistribution (+-) blocks of one pair (lambda, lambda'): every q'' in grid order, one
 // block of each mirror pair {q'', q'''} (V of the pair members are transposes of each other
 // when the quartet list is symmetric under the slot-3/slot-4 exchange, a.mirror; otherwise
-// every q'' block is queued and contracted on its own).  q'' is dealt to the wavefronts in
-// rounds of GPW consecutive points, so that every wavefront sees the whole grid; each
-// wavefront queues a segment of rounds in a fixed order (ballot + prefix count), then
+// every q'' block is queued and contracted on its own).  q'' is dealt out in rounds of 256
+// consecutive points, every fourth to a wavefront and one to each of its lanes, so that
+// every wavefront samples the whole grid evenly (mirror leaders, the lower-index member of
+// each pair, gather at low indices: contiguous shares would load the wavefronts unevenly);
+// each wavefront queues a segment of rounds in a fixed order (ballot + prefix count), then
 // contracts the queue.
 template <typename R, int NB, int NT>
 __device__ __forceinline__ void redistribution_blocks(
@@ -834,24 +836,25 @@ __device__ __forceinline__ void redistribution_blocks(
     int r, bool glane, typename CT<R>::T *Xg, typename CT<R>::T *Pg, const int *sg_d,
     const int *skl, int *Qw, const typename CT<R>::T *Xw, int2 *Gq, unsigned short *Lw,
     const PairIn &pi, const double (&invn)[NT], const double (&n1)[NT], Acc<NT> &acc) {
-  constexpr int GPW = 64 / NB;
   const unsigned long long lt = (1ull << lane) - 1ull;
   const bool pack = c.N <= 32768;
   const bool mir = a.mirror != 0;
   const Fold fp(c, pi, 1);
-  const int nk = (c.N + 4 * GPW - 1) / (4 * GPW);
-  const int KSEG = a.qseg / GPW;
-  // grid digits of the per-round step 4 GPW of q''
-  const int4 DK = make_int4((4 * GPW) % c.g0, ((4 * GPW) / c.g0) % c.g1, (4 * GPW) / (c.g0 * c.g1), 0);
+  const int nk = (c.N + 255) / 256;
+  const int KSEG = a.qseg / 64;
+  // grid digits of the per-round step 256 of q'' (one carry per digit at most: each step
+  // digit is below its grid dimension)
+  const int4 DK = make_int4(256 % c.g0, (256 / c.g0) % c.g1, 256 / (c.g0 * c.g1), 0);
   for (int k0 = 0; k0 < nk; k0 += KSEG) {
     const int k1 = min(nk, k0 + KSEG);
     int cnt = 0;
-    // the grid digits of q'' advance arithmetically by DK per round (no index-table load)
-    int iq2 = (k0 * 4 + wave) * GPW + gw;
+    // the grid digits of q'' advance arithmetically by DK per round (no index-table load);
+    // past the grid (q'' >= N, never queued) they run on unchecked
+    int iq2 = (k0 * 64 + lane) * 4 + wave;
     int4 d2 = c.qn[min(iq2, c.N - 1)];
     for (int k = k0; k < k1; ++k) {
       const int iq2c = iq2, iq3c = fp(c, -1, iq2, d2);
-      iq2 += 4 * GPW;
+      iq2 += 256;
       d2.x += DK.x;
       const int cx = d2.x >= c.g0;
       d2.x -= cx ? c.g0 : 0;
@@ -859,7 +862,7 @@ __device__ __forceinline__ void redistribution_blocks(
       const int cy = d2.y >= c.g1;
       d2.y -= cy ? c.g1 : 0;
       d2.z += DK.z + cy;
-      const bool lead = glane && iq2c < c.N && (!mir || iq2c <= iq3c) && r == 0;
+      const bool lead = iq2c < c.N && (!mir || iq2c <= iq3c);
       const unsigned long long lb = __ballot(lead);
       if (lead) Qw[cnt + __popcll(lb & lt)] = pack ? (iq2c | (iq3c << 15)) : iq2c;
       cnt += __popcll(lb);
