@@ -57,9 +57,9 @@ PEAK_FP32_VALU = 157.3e12
 # kernel sources without comments, the hipcc flags and the ROCm release they were taken
 # with.  The chip issues at most one wave64 FP64 VALU instruction per CU per cycle: 256 CUs
 # x 2.4 GHz.
-COUNTERS_FP64 = {"build_key": "2c3e90769fc20e92", "source": "profiles/k_rates_diamond8x8x8_fp64.md",
-                 "traffic_bytes": 1108404745.0, "valu_insts": 383751068131.0,
-                 "fp64_insts": 194092920412.0, "mfma_insts": 0.0}
+COUNTERS_FP64 = {"build_key": "d954640e31683e08", "source": "profiles/k_rates_diamond8x8x8_fp64.md",
+                 "traffic_bytes": 1499867874.9, "valu_insts": 371329246343.0,
+                 "fp64_insts": 198240618415.0, "mfma_insts": 0.0}
 VALU_ISSUE_PER_S = 256 * 2.4e9
 
 
