@@ -902,7 +902,9 @@ __device__ __forceinline__ int sorted_scan(const Crystal &c, const RateArgs &a, 
 
 // One segment, rounds [k0, k1), of the scan of ++ (CH = 0) or -- (CH = 2): the blocks with
 // a kept process are appended to the queue (tagged with bit 30 for --).  The sorted list is
-// dealt to the wavefronts in rounds of GPW consecutive points.
+// dealt out in rounds of 4 GPW consecutive points, every fourth point to a wavefront, so
+// that the four wavefronts sample the list (and its blocks with kept processes, which
+// gather at low frequencies) evenly.
 template <int NB, int CH>
 __device__ __forceinline__ void sorted_segment(const Crystal &c, const RateArgs &a, int wave,
                                                int lane, int gw, int r, bool glane,
@@ -949,8 +951,7 @@ __device__ __forceinline__ void sorted_segment(const Crystal &c, const RateArgs 
   int ns = 0;
   for (int i0 = 0; i0 < npt; i0 += 64) {
     const int i = i0 + lane;
-    const int kr = i / GPW;
-    const int p = ((k0 + kr) * 4 + wave) * GPW + (i - kr * GPW);
+    const int p = ((k0 * GPW + i) << 2) + wave;
     bool sv = false;
     int iq2 = 0, iq3 = 0;
     if (i < npt && p < nscan) {
