@@ -57,9 +57,9 @@ PEAK_FP32_VALU = 157.3e12
 # kernel sources without comments, the hipcc flags and the ROCm release they were taken
 # with.  The chip issues at most one wave64 FP64 VALU instruction per CU per cycle: 256 CUs
 # x 2.4 GHz.
-COUNTERS_FP64 = {"build_key": "d954640e31683e08", "source": "profiles/k_rates_diamond8x8x8_fp64.md",
-                 "traffic_bytes": 1499867874.9, "valu_insts": 371329246343.0,
-                 "fp64_insts": 198240618415.0, "mfma_insts": 0.0}
+COUNTERS_FP64 = {"build_key": "42273f4a4a331f8a", "source": "profiles/k_rates_diamond8x8x8_fp64.md",
+                 "traffic_bytes": 786011781.7, "valu_insts": 372895364501.0,
+                 "fp64_insts": 199679041405.0, "mfma_insts": 0.0}
 VALU_ISSUE_PER_S = 256 * 2.4e9
 
 
