@@ -106,6 +106,36 @@ def test_ragged_grids_second_shell(fp4, grid, rc, sb, mask, T):
     assert np.array_equal(call[targets], cnt)
 
 
+def test_ragged_tail_small_segments(fp4):
+    """A 7x6x8 grid (336 points: the redistribution queueing takes two rounds of 256 points,
+    the second ragged) with the smallest queue and list segments (64 and 64: one round per
+    queue segment, the ++/-- scans flushed many times, lists evaluated in many passes):
+    counts equal and FP64 rates within 1e-12 of the default segments', FP32 counts equal;
+    the oracle's counts exact on 32 sampled modes and its rates on three (FP64 1e-10, FP32
+    1e-4).  First-shell FC4 keeps the oracle's rates to a few seconds."""
+    _say("case: ragged tail, small segments")
+    inst = synth.diamond_instance((7, 6, 8), synth.configs.RC_FIRST, seed=41, T=(300.0, 800.0))
+    nm = inst.nmodes
+    rng = np.random.default_rng(4)
+    tc = np.unique(np.concatenate([[3, nm - 1], rng.choice(nm, 30, replace=False)]))
+    tr = np.array([3, nm // 2, nm - 1])
+    with _ctx(fp4, inst) as c:
+        r_d, _, c_d = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+        c.set_param(fp4.FP4_PARAM_QSEG, 64)
+        c.set_param(fp4.FP4_PARAM_LSEG, 64)
+        r_s, _, c_s = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP64)
+        r32, _, c32 = c.compute_rates4(inst.T, 1.0, 7, fp4.FP4_FP32)
+    assert c_d.sum() > 0
+    assert np.array_equal(c_s, c_d) and np.array_equal(c32, c_d)
+    assert _rel(r_s, r_d) <= 1e-12
+    _, _, c_o = _oracle(inst, inst.T, 1.0, 7, tc, want_rates=False)
+    assert np.array_equal(c_d[tc], c_o)
+    r_o, _, c_o3 = _oracle(inst, inst.T, 1.0, 7, tr)
+    assert np.array_equal(c_d[tr], c_o3)
+    assert _rel(r_d[:, tr], r_o) <= RTOL64
+    assert _rel(r32[:, tr], r_o) <= RTOL32
+
+
 def test_debug_matrix_elements(fp4):
     """V through the library's own contraction (W'', F, E3 F E4^T) against Eq. V4 evaluated
     literally by the oracle, all three channels, Umklapp included."""
