@@ -57,21 +57,22 @@ PEAK_FP32_VALU = 157.3e12
 # kernel sources without comments, the hipcc flags and the ROCm release they were taken
 # with.  The chip issues at most one wave64 FP64 VALU instruction per CU per cycle: 256 CUs
 # x 2.4 GHz.
-COUNTERS_FP64 = {"build_key": "42273f4a4a331f8a", "source": "profiles/k_rates_diamond8x8x8_fp64.md",
-                 "traffic_bytes": 786011781.7, "valu_insts": 372895364501.0,
-                 "fp64_insts": 199679041405.0, "mfma_insts": 0.0}
+COUNTERS_FP64 = {"build_key": "d8c1ba0d0838c13c", "source": "profiles/k_rates_diamond8x8x8_fp64.md",
+                 "traffic_bytes": 889599669.0, "valu_insts": 373089497237.0,
+                 "fp64_insts": 199695849085.0, "mfma_insts": 0.0}
 VALU_ISSUE_PER_S = 256 * 2.4e9
 
 
 def kernel_build_key():
-    """sha256 (first 16 hex digits) of what the rate kernel's machine code depends on: its
-    sources with comments and blank lines removed (a comment edit does not invalidate the
-    counter readings), the hipcc flags of the build, and the ROCm release."""
+    """sha256 (first 16 hex digits) of what the rate kernel's launches depend on: its sources
+    and the host code that chooses their shapes (q' chunks, segments), with comments and
+    blank lines removed (a comment edit does not invalidate the counter readings), the hipcc
+    flags of the build, and the ROCm release."""
     import hashlib
     import re
     from paper_2104_04895_amd import build as hb
     h = hashlib.sha256()
-    for f in ("fp4_kernels.hip", "fp4_device.h", "fp4_internal.h"):
+    for f in ("fp4_kernels.hip", "fp4_device.h", "fp4_internal.h", "fp4_api.cpp"):
         with open(os.path.join(ROOT, "paper_2104_04895_amd", "csrc", f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)

@@ -330,7 +330,7 @@ int fp4_batch_add(fp4_batch *b, fp4_ctx *ctx);
  *           [nT][nq_i*nb_i] (1/ps)
  *   counts  host, concatenated blocks [nq_i*nb_i][3], or NULL
  * Each instance uses its context's q'-chunk (FP4_PARAM_QCHUNK or fp4_autotune), or the
- * automatic choice of a single call (at most 16) if unset.  Synchronous. */
+ * automatic choice of a single call (at most 8) if unset.  Synchronous. */
 int fp4_batch_compute(fp4_batch *b, const double *T, int32_t nT, double scalebroad,
                       uint32_t mask, int32_t precision, double *rates, int64_t *counts);
 
